@@ -1,0 +1,258 @@
+"""ORACLE -- test infrastructure only.
+
+Plain FP64 CPU reference for the worldline Wilson-loop average (Mazur & Heyl,
+arXiv:1407.7486).  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package; the product path
+(the GPU library and its binding) never does and shares no code with it.
+
+Contents
+  * ``evaluate``      -- per-loop phase / spin exponent / Wilson loop and the
+                         contiguous group sums (C library ``wl_oracle.c``).
+  * ``stats``         -- ensemble mean, group standard error and the
+                         delete-a-group jackknife (Sec. 4.2.3).
+  * closed forms      -- constant-field averages (Sec. 3.3): scalar
+                         theta/sinh(theta), spinor theta*coth(theta), and the
+                         exact finite-N scalar average of the discrete loop law.
+  * ``vloop_ensemble``-- an independent loop generator (i.i.d. Gaussian
+                         increments, closed by subtracting their mean) that
+                         samples the same discrete law as the d-loops of
+                         Sec. 2.1; used to cross-check the input generator.
+  * ``dloop_reference``-- the d-loop recursion of Sec. 2.1 written out in pure
+                         Python for tiny loops, from given normals.
+
+Parity notes: every function here is pinned by tests against values the
+mathematics fixes (closed forms, quadrature of the field, brute force on tiny
+inputs, exact identities).  See ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+CONST, SECH2, GAUSS, RATIONAL = 0, 1, 2, 3
+
+
+def build(verbose: bool = False) -> str:
+    """Compile wl_oracle.c -> liboracle.so with gcc (always recompiles)."""
+    global _lib
+    src = os.path.join(_HERE, "wl_oracle.c")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", src,
+           "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    _lib = None
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        d, i32, i64, vp = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
+                           ctypes.c_void_p)
+        lib.wlo_field_g.argtypes = [ctypes.c_int, d, d, d]
+        lib.wlo_field_g.restype = d
+        lib.wlo_field_b.argtypes = [ctypes.c_int, d, d, d]
+        lib.wlo_field_b.restype = d
+        lib.wlo_gauss_legendre.argtypes = [ctypes.c_int, vp, vp]
+        lib.wlo_gauss_legendre.restype = ctypes.c_int
+        lib.wlo_loop.argtypes = [vp, vp, i32, ctypes.c_int, d, d, d, d,
+                                 ctypes.c_int, vp, vp]
+        lib.wlo_loop.restype = ctypes.c_int
+        lib.wlo_evaluate.argtypes = [vp, vp, i64, i32, ctypes.c_int, d, d, vp,
+                                     i32, vp, i32, ctypes.c_int, ctypes.c_int,
+                                     i32, i32, vp, vp, vp, vp]
+        lib.wlo_evaluate.restype = ctypes.c_int
+        lib.wlo_max_threads.argtypes = []
+        lib.wlo_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().wlo_max_threads())
+
+
+# ------------------------------------------------------------------ fields
+def field_g(kind: int, eB0: float, lam: float, r2) -> np.ndarray:
+    """g(rho^2) = e A_phi / rho (phase integrand per unit cross product)."""
+    lib = _load()
+    r2 = np.atleast_1d(np.asarray(r2, dtype=np.float64))
+    return np.array([lib.wlo_field_g(kind, eB0, lam, float(v)) for v in r2])
+
+
+def field_b(kind: int, eB0: float, lam: float, r2) -> np.ndarray:
+    """b(rho^2) = e B (spin-factor integrand)."""
+    lib = _load()
+    r2 = np.atleast_1d(np.asarray(r2, dtype=np.float64))
+    return np.array([lib.wlo_field_b(kind, eB0, lam, float(v)) for v in r2])
+
+
+def gauss_legendre(nq: int):
+    t = np.empty(nq)
+    w = np.empty(nq)
+    if _load().wlo_gauss_legendre(nq, t.ctypes.data, w.ctypes.data) != 0:
+        raise ValueError("nq out of range 1..8")
+    return t, w
+
+
+# ------------------------------------------------------------- evaluation
+def loop(yx, yy, kind, eB0, lam, rho, T, nq=1):
+    """(phase, spin exponent) of one unit loop at one (rho_cm, T)."""
+    yx = np.ascontiguousarray(yx, dtype=np.float64)
+    yy = np.ascontiguousarray(yy, dtype=np.float64)
+    ph = ctypes.c_double()
+    sp = ctypes.c_double()
+    rc = _load().wlo_loop(yx.ctypes.data, yy.ctypes.data, yx.size, kind, eB0,
+                          lam, rho, T, nq, ctypes.byref(ph), ctypes.byref(sp))
+    if rc != 0:
+        raise ValueError("invalid loop arguments")
+    return ph.value, sp.value
+
+
+def evaluate(x, y, kind, eB0, lam, rho, T, spin, n_groups, nq=1,
+             per_loop=False, n_threads=0):
+    """Evaluate the whole (rho, T) grid over an ensemble.
+
+    x, y: (n_loops, N) unit-loop coordinates (FP32 inputs are promoted
+    exactly to FP64).  Returns a dict with ``group_sums`` of shape
+    (n_groups, n_rho, n_T) and, if ``per_loop``, ``w``, ``phase`` and
+    ``spin`` of shape (n_loops, n_rho, n_T).
+    """
+    X = np.ascontiguousarray(x, dtype=np.float64)
+    Y = np.ascontiguousarray(y, dtype=np.float64)
+    n_loops, n = X.shape
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    nr, nt = rho.size, T.size
+    gs = np.zeros((n_groups, nr, nt))
+    w = ph = sp = None
+    ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+    if per_loop:
+        w = np.zeros((n_loops, nr, nt))
+        ph = np.zeros((n_loops, nr, nt))
+        sp = np.zeros((n_loops, nr, nt))
+    rc = _load().wlo_evaluate(X.ctypes.data, Y.ctypes.data, n_loops, n, kind,
+                              eB0, lam, rho.ctypes.data, nr, T.ctypes.data, nt,
+                              int(spin), nq, n_groups, n_threads,
+                              gs.ctypes.data, ptr(w), ptr(ph), ptr(sp))
+    if rc != 0:
+        raise ValueError(f"oracle evaluate failed ({rc})")
+    out = {"group_sums": gs}
+    if per_loop:
+        out.update(w=w, phase=ph, spin=sp)
+    return out
+
+
+# ------------------------------------------------------------ statistics
+def stats(group_sums, n_loops):
+    """Mean, group standard error and delete-a-group jackknife error.
+
+    Sec. 4.2.3: group means <W>_Gj = (N_G/N_l) sum_{i in G_j} W_i; the mean
+    is their average (= the plain loop average); the error is the standard
+    error of the group means, sqrt(sum_j (<W>_Gj - <W>)^2 / (N_G (N_G-1))).
+    The delete-a-group jackknife re-estimates the mean with each group left
+    out, theta_(j), and takes sqrt((N_G-1)/N_G * sum_j (theta_(j) - mean
+    of theta_(.))^2).
+    """
+    S = np.asarray(group_sums, dtype=np.float64)
+    G = S.shape[0]
+    per = n_loops / G
+    gmeans = S / per
+    mean = S.sum(axis=0) / n_loops
+    if G > 1:
+        err = np.sqrt(((gmeans - mean) ** 2).sum(axis=0) / (G * (G - 1)))
+        total = S.sum(axis=0)
+        loo = (total - S) / (n_loops - per)
+        jk = np.sqrt((G - 1) / G * ((loo - loo.mean(axis=0)) ** 2).sum(axis=0))
+    else:
+        err = np.full_like(mean, np.nan)
+        jk = np.full_like(mean, np.nan)
+    return mean, err, jk
+
+
+# ----------------------------------------------------------- closed forms
+def w_scalar_continuum(theta):
+    """Constant field, scalar: <W> = eBT / sinh(eBT) (Sec. 3.3)."""
+    th = np.asarray(theta, dtype=np.float64)
+    with np.errstate(invalid="ignore", over="ignore"):
+        return np.where(th == 0, 1.0, th / np.sinh(th))
+
+
+def w_spinor_continuum(theta):
+    """Constant field, spinor: <W> = eBT coth(eBT) (Sec. 3.3)."""
+    th = np.asarray(theta, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(th == 0, 1.0, th / np.tanh(th))
+
+
+def w_scalar_finite_n(theta, n_ppl):
+    """Exact constant-field scalar average over the N-point discrete loop law
+    exp(-(N/4) sum |y_{i+1}-y_i|^2) (CM fixed): the flux through an N-gon is
+    eB T times its signed area, a quadratic form in Gaussians whose
+    characteristic function is prod_{k=1}^{N-1} (1 + theta^2 cot^2(pi k/N)
+    / N^2)^(-1/2).  Tends to theta/sinh(theta) as N grows."""
+    th = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    k = np.arange(1, n_ppl)
+    c2 = 1.0 / np.tan(np.pi * k / n_ppl) ** 2
+    out = np.empty_like(th)
+    for i, t in enumerate(th):
+        out[i] = math.exp(-0.5 * np.log1p(t * t * c2 / n_ppl ** 2).sum())
+    return out
+
+
+# ------------------------------------------------------------- generators
+def vloop_ensemble(n_loops, n_ppl, rng):
+    """Independent sampler of the discrete unit-loop law (2-D, CM at 0):
+    i.i.d. increments of variance 2/N per component, minus their mean (which
+    closes the loop), cumulative sum, then the centre of mass removed."""
+    d = rng.standard_normal((n_loops, n_ppl, 2)) * math.sqrt(2.0 / n_ppl)
+    d -= d.mean(axis=1, keepdims=True)
+    pts = np.cumsum(d, axis=1)
+    pts -= pts.mean(axis=1, keepdims=True)
+    return pts[..., 0].copy(), pts[..., 1].copy()
+
+
+def dloop_reference(z, n_ppl):
+    """The d-loop recursion of Sec. 2.1 in pure Python (tiny loops only):
+    start from one point at the origin, then per level N_k = 2, 4, ..., N add
+    the points between existing neighbours at their midpoint plus a normal of
+    variance 1/N_k per component; finally shift the centre of mass to 0.
+    z: the normals, consumed level by level, x then y per new point."""
+    x = [0.0] * n_ppl
+    y = [0.0] * n_ppl
+    it = iter(list(map(float, z)))
+    nk = 2
+    while nk <= n_ppl:
+        h = n_ppl // nk
+        sd = 1.0 / math.sqrt(nk)
+        for q in range(1, nk, 2):
+            i = q * h
+            left, right = x[i - h], x[(i + h) % n_ppl]
+            x[i] = 0.5 * (left + right) + sd * next(it)
+            left, right = y[i - h], y[(i + h) % n_ppl]
+            y[i] = 0.5 * (left + right) + sd * next(it)
+        nk *= 2
+    mx = sum(x) / n_ppl
+    my = sum(y) / n_ppl
+    return (np.array([v - mx for v in x]), np.array([v - my for v in y]))
+
+
+def signed_area(x, y):
+    """Shoelace signed area of closed polygons along the last axis."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return 0.5 * (x * np.roll(y, -1, axis=-1) - y * np.roll(x, -1, axis=-1)).sum(axis=-1)

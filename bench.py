@@ -1,0 +1,155 @@
+"""Throughput benchmark of the Wilson-loop ensemble average on one MI355X.
+
+One step = one full evaluation of the workload's (rho_cm, T) grid over the
+device-resident loop ensemble: the main kernel (segment sums, per-loop
+epilogue, group accumulation), the sub-range reduction and the group
+statistics.  The ensemble is uploaded before timing.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p99 ms"
+
+# VALU issue slots per segment evaluation of the FP32 compensated kernel
+# (quarter-rate transcendentals count 4 slots), by field kind and spin.
+SLOTS_FP32C = {("sech2", 1): 41, ("sech2", 0): 36, ("gauss", 1): 29,
+               ("gauss", 0): 24, ("rational", 1): 18, ("rational", 0): 13,
+               ("const", 1): 8, ("const", 0): 8}
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed FP32 issue rate)
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--workload", default="sech2_spinor_64k")
+    ap.add_argument("--cpu-loops", type=int, default=64,
+                    help="loops in the oracle's timed CPU sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU split is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1407_7486_amd as wl
+    import wlinputs
+
+    cfg = wlinputs.WORKLOADS[args.workload]
+    kind, spin = cfg["kind"], cfg["spin"]
+    kname = KIND_NAMES[kind]
+    t0 = time.time()
+    x, y = wlinputs.dloop_ensemble(cfg["n_loops"], cfg["n_ppl"], seed=cfg["seed"])
+    log(f"[bench] generated {cfg['n_loops']}x{cfg['n_ppl']} d-loops in {time.time() - t0:.1f}s")
+    rho = wlinputs.rho_grid(*cfg["rho"])
+    T = wlinputs.t_grid(*cfg["T"])
+    G = cfg["n_groups"]
+    seg_per_step = cfg["n_loops"] * cfg["n_ppl"] * rho.size * T.size
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = wl.wl_create(0, stream.cuda_stream)
+    t0 = time.time()
+    ens = wl.wl_ensemble_upload(ctx, x, y, G)
+    log(f"[bench] uploaded ensemble in {time.time() - t0:.1f}s")
+    d_rho = torch.tensor(rho, dtype=torch.float64, device=dev)
+    d_T = torch.tensor(T, dtype=torch.float64, device=dev)
+    d_sums = torch.empty((G, rho.size, T.size), dtype=torch.float64, device=dev)
+    d_mean = torch.empty((rho.size, T.size), dtype=torch.float64, device=dev)
+    d_err = torch.empty_like(d_mean)
+    fld = wl.field(kind, cfg["eB0"], cfg["lam"])
+
+    def run(prec, warmup, steps):
+        for _ in range(warmup):
+            wl.wl_average_async(ctx, ens, fld, d_rho, d_T, spin, prec, d_mean, d_err, d_sums)
+        torch.cuda.synchronize()
+        wl.wl_set_timing(ctx, True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(steps):
+            wl.wl_average_async(ctx, ens, fld, d_rho, d_T, spin, prec, d_mean, d_err, d_sums)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t_start
+        k_ms, n = wl.wl_kernel_ms_total(ctx)
+        wl.wl_set_timing(ctx, False)
+        if not bool(torch.isfinite(d_mean).all()):
+            raise RuntimeError("non-finite result")
+        return dt, k_ms / n
+
+    log(f"[bench] fp32c: warmup {args.warmup}, steps {args.steps}")
+    dt, k_ms = run(wl.WL_FP32C, args.warmup, args.steps)
+    value = seg_per_step * args.steps / dt
+    log(f"[bench] fp32c {value:.4e} seg/s, kernel {k_ms:.1f} ms")
+    mean32 = d_mean.cpu().numpy()
+    fp64 = None
+    if args.fp64_steps > 0:
+        log(f"[bench] fp64: steps {args.fp64_steps}")
+        dt64, k64 = run(wl.WL_FP64, 0, args.fp64_steps)
+        v64 = seg_per_step * args.fp64_steps / dt64
+        mean64 = d_mean.cpu().numpy()
+        scale = np.maximum(np.abs(mean64), 1.0)
+        fp64 = {"value": v64, "ms_per_step": 1e3 * dt64 / args.fp64_steps,
+                "kernel_ms": k64, "steps": args.fp64_steps,
+                "fp32c_over_fp64": value / v64,
+                "max_rel_mean_diff_fp32c_vs_fp64": float(np.max(np.abs(mean32 - mean64) / scale))}
+        log(f"[bench] fp64 {v64:.4e} seg/s, kernel {k64:.1f} ms")
+
+    slots = SLOTS_FP32C[(kname, spin)]
+    achieved = seg_per_step * slots / (k_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
+                "kernel": "k_average<sech2,spin,fp32c>", "kernel_ms": k_ms,
+                "slots_per_segment": slots}
+
+    cpu = None
+    if args.cpu_loops > 0:
+        import oracle
+        nl = args.cpu_loops
+        t0 = time.perf_counter()
+        oracle.evaluate(x[:nl], y[:nl], kind, cfg["eB0"], cfg["lam"], rho, T, spin,
+                        1, n_threads=0)
+        dtc = time.perf_counter() - t0
+        segs = nl * cfg["n_ppl"] * rho.size * T.size
+        cpu = {"value": segs / dtc, "unit": "segment-evals/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"first {nl} loops of the ensemble, full {rho.size}x{T.size} grid, "
+                         f"FP64, {dtc:.1f} s wall"}
+        log(f"[bench] cpu oracle {segs / dtc:.4e} seg/s on {cpu['cores']} threads")
+
+    wl.wl_ensemble_free(ens)
+    wl.wl_destroy(ctx)
+    out = {
+        "metric": METRIC, "value": value, "unit": "segment-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n_loops": cfg["n_loops"],
+                   "n_ppl": cfg["n_ppl"], "n_rho": int(rho.size), "n_T": int(T.size),
+                   "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
+                   "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
+        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

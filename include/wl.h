@@ -1,0 +1,190 @@
+/*
+ * wl.h -- C ABI of the MI355X (gfx950) worldline Wilson-loop library.
+ *
+ * The library evaluates the loop-cloud ("worldline numerics") estimate of
+ * the Wilson-loop expectation value <W(x_cm, T)> in a cylindrically
+ * symmetric magnetic field B(rho) z^ (Mazur & Heyl, "Parallel Worldline
+ * Numerics: Implementation and Error Analysis", arXiv:1407.7486):
+ *
+ *   - unit loops y(tau) of N points are scaled by sqrt(T) and moved to the
+ *     centre of mass x_cm = (rho_cm, 0) (Sec. 2.1, Loop Generation);
+ *   - each straight segment contributes the phase
+ *       (x^i y^{i+1} - y^i x^{i+1}) * int_0^1 e A_phi(rho(t))/rho(t) dt
+ *     (Sec. 3.2.1, Eqs. rhoi..Ci), evaluated with the midpoint rule;
+ *   - spinors add cosh(e int_0^T B dtau) (Sec. 3.2.2, Eq. Wfermfpl);
+ *   - per loop w = cos(Phi) * cosh(S)  (scalar: cos(Phi));
+ *   - loops fall into G contiguous groups; the library returns the group
+ *     sums of w, the mean and the standard error of the group means
+ *     (Sec. 4.2.3, Grouping Worldlines), which for the mean equals the
+ *     delete-a-group jackknife error.
+ *
+ * Conventions
+ *   - Every function returns WL_OK (0) or a negative WL_E* code.  Functions
+ *     taking a context store a message retrievable with wl_last_error().
+ *     Nothing is printed.
+ *   - A context is bound to one device and one HIP stream; it must not be
+ *     used from two host threads at once.
+ *   - Grid point p = j * n_T + k for rho[j], T[k]; arrays "[n_rho][n_T]" are
+ *     row-major with T fastest; group sums are [G][n_rho][n_T].
+ *   - Unless an argument says "device", pointers are host pointers.
+ */
+#ifndef WL_H
+#define WL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define WL_OK 0
+#define WL_EINVAL (-1)  /* invalid argument (message says which)           */
+#define WL_ENOMEM (-2)  /* host or device allocation failed                */
+#define WL_EHIP (-3)    /* HIP runtime error (message has the HIP string)  */
+#define WL_ENODEV (-4)  /* no such device, or not a gfx950 device          */
+
+/* ---- field kinds (Sec. 3.1, Cylindrical Magnetic Fields) --------------
+ * The charge is absorbed: eB0 is e times the field on the axis, lambda
+ * the tube width (ignored by WL_CONST).  With b = eB(rho) and
+ * g = e A_phi(rho)/rho = e Phi_B(rho) / (2 pi rho^2):
+ *   WL_CONST    b = eB0                         g = eB0/2
+ *   WL_SECH2    b = eB0 sech^2(rho/lambda)      g = eB0 lambda [rho tanh(rho/
+ *               lambda) - lambda ln cosh(rho/lambda)] / rho^2
+ *   WL_GAUSS    b = eB0 exp(-rho^2/lambda^2)    g = eB0 lambda^2 (1 - exp(
+ *               -rho^2/lambda^2)) / (2 rho^2)
+ *   WL_RATIONAL the paper's validation profile f = rho^2/(lambda^2+rho^2)
+ *               (Sec. 6) with flux F = eB0 lambda^2/2:
+ *               b = eB0 lambda^4/(lambda^2+rho^2)^2,
+ *               g = eB0 lambda^2 / (2 (lambda^2+rho^2))                    */
+#define WL_CONST 0
+#define WL_SECH2 1
+#define WL_GAUSS 2
+#define WL_RATIONAL 3
+
+typedef struct wl_field {
+  int32_t kind;     /* WL_CONST .. WL_RATIONAL                             */
+  int32_t reserved; /* must be 0                                           */
+  double eB0;       /* finite                                              */
+  double lambda;    /* > 0 and finite for all kinds but WL_CONST           */
+} wl_field;
+
+/* ---- precision modes ---------------------------------------------------
+ * WL_FP32C  FP32 segment arithmetic with compensated (Kahan) phase and
+ *           spin sums; FP64 per-loop epilogue and FP64 group sums.
+ * WL_FP32   the same with plain FP32 sums (precision-study mode).
+ * WL_FP64   FP64 throughout.                                               */
+#define WL_FP32C 0
+#define WL_FP32 1
+#define WL_FP64 2
+
+/* ---- ensemble upload flags -------------------------------------------- */
+#define WL_HOST_PTR 0   /* y_x, y_y are host pointers                       */
+#define WL_DEVICE_PTR 1 /* y_x, y_y are device pointers on the ctx device   */
+
+typedef struct wl_ctx wl_ctx;
+typedef struct wl_ens wl_ens;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (for example torch.cuda.current_stream().cuda_stream) or NULL for the
+ * default stream; every launch and copy of this context goes to it.
+ * Errors: WL_ENODEV (no such device / not gfx950), WL_ENOMEM, WL_EINVAL
+ * (out == NULL). */
+int wl_create(wl_ctx** out, int device, void* hip_stream);
+
+/* Free the context and its scratch buffers (ensembles are freed with
+ * wl_ensemble_free).  NULL is allowed. */
+int wl_destroy(wl_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none).  The pointer stays
+ * valid until the next call on ctx. */
+const char* wl_last_error(const wl_ctx* ctx);
+
+/* Static description of a return code. */
+const char* wl_strerror(int code);
+
+/* Library version string (static storage). */
+const char* wl_version(void);
+
+/* Ensemble upload (the device-resident loop cloud, Appendix: the loops are
+ * copied to device memory once and persist across evaluations).
+ * y_x, y_y: unit-loop coordinates, FP32, [n_loops][n_ppl] row-major (the
+ * points of one loop contiguous), host or device memory per `flags`.  The
+ * data are COPIED; the caller keeps ownership of its buffers.  The library
+ * also derives per-segment quantities used by the FP32 kernels.
+ * Requirements: n_loops >= 1, n_ppl >= 2, 1 <= n_groups, n_loops %
+ * n_groups == 0 (equal groups, Sec. 4.2.3), all coordinates finite.
+ * The call is synchronous (it returns once the copy is complete).
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
+                       int64_t n_loops, int32_t n_ppl, int32_t n_groups,
+                       int32_t flags, wl_ens** out);
+
+/* Free an ensemble (NULL allowed).  Must be called before wl_destroy of the
+ * context that created it. */
+int wl_ensemble_free(wl_ens* ens);
+
+/* Shape of an uploaded ensemble (any output pointer may be NULL). */
+int wl_ensemble_info(const wl_ens* ens, int64_t* n_loops, int32_t* n_ppl,
+                     int32_t* n_groups);
+
+/* Wilson-loop ensemble average over the grid rho[n_rho] x T[n_T]
+ * (Sec. 3.2 for w per loop, Sec. 4.2.3 for groups and error).
+ * rho >= 0 and T > 0, all finite; spin 0 = scalar, 1 = spinor; precision
+ * one of WL_FP32C, WL_FP32, WL_FP64.
+ * Outputs (host, caller-owned, each may be NULL):
+ *   mean       [n_rho][n_T]    (1/N_l) sum_l w_l
+ *   err        [n_rho][n_T]    standard error of the group means (NaN if
+ *                              G == 1); equals the delete-a-group jackknife
+ *   group_sums [G][n_rho][n_T] sum of w over each group's loops, FP64
+ * n_rho == 0 or n_T == 0 is an empty grid: WL_OK, nothing written.
+ * Synchronous.  Results do not depend on the launch schedule: every group
+ * sum has a single owner and a fixed summation order.
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+               const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+               int32_t spin, int32_t precision, double* mean, double* err,
+               double* group_sums);
+
+/* As wl_average, but every array is DEVICE memory on the ctx device and
+ * the call only enqueues work on the ctx stream (no host synchronisation).
+ * d_rho, d_T must stay valid and unchanged until the work completes, and
+ * their values are NOT validated (the caller guarantees rho >= 0, T > 0).
+ * d_group_sums is required; d_mean and d_err may be NULL.  The library may
+ * use its own device scratch buffer, so calls on one ctx are serialised on
+ * its stream. */
+int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                     const double* d_rho, int32_t n_rho, const double* d_T,
+                     int32_t n_T, int32_t spin, int32_t precision,
+                     double* d_mean, double* d_err, double* d_group_sums);
+
+/* Per-loop values for loops loop0 .. loop0+n_loops-1 on the grid (for
+ * loop-by-loop checks).  Same kernels as wl_average.  Outputs (host, each
+ * may be NULL) of shape [n_loops][n_rho][n_T]:
+ *   phase     Phi in radians
+ *   spin_exp  S = e int_0^T B dtau (0 is written when spin == 0)
+ *   w         cos(Phi) * (spin ? cosh(S) : 1)
+ * n_loops * n_rho * n_T must not exceed 2^27.
+ * Synchronous.  Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                int32_t spin, int32_t precision, int64_t loop0,
+                int64_t n_loops, double* phase, double* spin_exp, double* w);
+
+/* Kernel timing: when enabled, the main evaluation kernel of each
+ * wl_average / wl_average_async call is bracketed by HIP events on the ctx
+ * stream.  wl_set_timing(ctx, 1) also forgets earlier records.
+ * wl_last_kernel_ms waits for the last recorded launch and returns its
+ * duration in milliseconds; wl_kernel_ms_total waits for all of them and
+ * returns the sum of their durations and their count.  Both return
+ * WL_EINVAL if nothing was recorded. */
+int wl_set_timing(wl_ctx* ctx, int32_t enable);
+int wl_last_kernel_ms(wl_ctx* ctx, double* ms);
+int wl_kernel_ms_total(wl_ctx* ctx, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WL_H */

@@ -1,0 +1,227 @@
+"""Python binding of the MI355X worldline Wilson-loop library (libwl.so).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels behind the C ABI of ``include/wl.h``; the functions here carry the
+same names.  Host arrays are numpy; device arrays are torch tensors on the
+context's device (torch supplies device memory and streams).
+
+If ``libwl.so`` has not been built the import raises: there is no CPU
+fallback.  Build it with ``python -m paper_1407_7486_amd.build`` or
+``__graft_entry__.build()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwl.so")
+
+WL_OK, WL_EINVAL, WL_ENOMEM, WL_EHIP, WL_ENODEV = 0, -1, -2, -3, -4
+WL_CONST, WL_SECH2, WL_GAUSS, WL_RATIONAL = 0, 1, 2, 3
+WL_FP32C, WL_FP32, WL_FP64 = 0, 1, 2
+WL_HOST_PTR, WL_DEVICE_PTR = 0, 1
+
+# every entry point declared in include/wl.h
+EXPORTS = (
+    "wl_create", "wl_destroy", "wl_last_error", "wl_strerror", "wl_version",
+    "wl_ensemble_upload", "wl_ensemble_free", "wl_ensemble_info",
+    "wl_average", "wl_average_async", "wl_per_loop", "wl_set_timing",
+    "wl_last_kernel_ms", "wl_kernel_ms_total",
+)
+
+
+class WLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class wl_field(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eB0", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: the HIP library has not been built "
+        "(run python -m paper_1407_7486_amd.build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_sigs = {
+    "wl_create": ([ctypes.POINTER(_vp), ctypes.c_int, _vp], ctypes.c_int),
+    "wl_destroy": ([_vp], ctypes.c_int),
+    "wl_last_error": ([_vp], ctypes.c_char_p),
+    "wl_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "wl_version": ([], ctypes.c_char_p),
+    "wl_ensemble_upload": ([_vp, _vp, _vp, _i64, _i32, _i32, _i32,
+                            ctypes.POINTER(_vp)], ctypes.c_int),
+    "wl_ensemble_free": ([_vp], ctypes.c_int),
+    "wl_ensemble_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                          ctypes.POINTER(_i32)], ctypes.c_int),
+    "wl_average": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
+                    _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "wl_average_async": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp,
+                          _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "wl_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
+                     _i32, _i32, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "wl_set_timing": ([_vp, _i32], ctypes.c_int),
+    "wl_last_kernel_ms": ([_vp, ctypes.POINTER(_d)], ctypes.c_int),
+    "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
+                           ctypes.c_int),
+}
+for _name, (_args, _res) in _sigs.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def _check(rc, ctx=None):
+    if rc != WL_OK:
+        msg = _lib.wl_last_error(ctx).decode() if ctx else ""
+        raise WLError(rc, msg or _lib.wl_strerror(rc).decode())
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _host_f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def field(kind, eB0, lam=1.0):
+    return wl_field(int(kind), 0, float(eB0), float(lam))
+
+
+def wl_version():
+    return _lib.wl_version().decode()
+
+
+def wl_strerror(code):
+    return _lib.wl_strerror(code).decode()
+
+
+def wl_create(device=0, stream=None):
+    """Context on HIP device `device`; `stream` is a raw hipStream_t value
+    (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+    ctx = _vp()
+    rc = _lib.wl_create(ctypes.byref(ctx), int(device), stream)
+    if rc != WL_OK:
+        raise WLError(rc, wl_strerror(rc))
+    return ctx
+
+
+def wl_destroy(ctx):
+    _check(_lib.wl_destroy(ctx))
+
+
+def wl_last_error(ctx):
+    return _lib.wl_last_error(ctx).decode()
+
+
+def wl_ensemble_upload(ctx, y_x, y_y, n_groups):
+    """Upload unit loops [n_loops][n_ppl] (FP32).  numpy arrays are host
+    memory; torch CUDA tensors are device memory."""
+    dev = not isinstance(y_x, np.ndarray)
+    if dev:
+        if y_x.dtype != _torch().float32 or not y_x.is_contiguous() \
+                or not y_y.is_contiguous() or y_x.shape != y_y.shape:
+            raise ValueError("device coordinates must be contiguous float32 of one shape")
+    else:
+        y_x = np.ascontiguousarray(y_x, dtype=np.float32)
+        y_y = np.ascontiguousarray(y_y, dtype=np.float32)
+        if y_x.shape != y_y.shape or y_x.ndim != 2:
+            raise ValueError("coordinates must be two arrays of shape (n_loops, n_ppl)")
+    n_loops, n_ppl = y_x.shape
+    ens = _vp()
+    _check(_lib.wl_ensemble_upload(ctx, _ptr(y_x), _ptr(y_y), n_loops, n_ppl,
+                                   int(n_groups),
+                                   WL_DEVICE_PTR if dev else WL_HOST_PTR,
+                                   ctypes.byref(ens)), ctx)
+    return ens
+
+
+def wl_ensemble_free(ens):
+    _check(_lib.wl_ensemble_free(ens))
+
+
+def wl_ensemble_info(ens):
+    nl, npl, ng = _i64(), _i32(), _i32()
+    _check(_lib.wl_ensemble_info(ens, ctypes.byref(nl), ctypes.byref(npl),
+                                 ctypes.byref(ng)))
+    return nl.value, npl.value, ng.value
+
+
+def wl_average(ctx, ens, fld, rho, T, spin, precision=WL_FP32C):
+    """Synchronous average; returns (mean, err, group_sums) as numpy arrays
+    of shapes (n_rho, n_T), (n_rho, n_T), (G, n_rho, n_T)."""
+    rho = _host_f64(rho)
+    T = _host_f64(T)
+    _, _, G = wl_ensemble_info(ens)
+    mean = np.zeros((rho.size, T.size))
+    err = np.zeros((rho.size, T.size))
+    sums = np.zeros((G, rho.size, T.size))
+    _check(_lib.wl_average(ctx, ens, ctypes.byref(fld), _ptr(rho), rho.size,
+                           _ptr(T), T.size, int(spin), int(precision),
+                           _ptr(mean), _ptr(err), _ptr(sums)), ctx)
+    return mean, err, sums
+
+
+def wl_average_async(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,
+                     d_err, d_group_sums):
+    """Enqueue an average on the context stream; all arrays are torch
+    float64 device tensors (d_mean / d_err may be None)."""
+    _check(_lib.wl_average_async(ctx, ens, ctypes.byref(fld), _ptr(d_rho),
+                                 d_rho.numel(), _ptr(d_T), d_T.numel(),
+                                 int(spin), int(precision), _ptr(d_mean),
+                                 _ptr(d_err), _ptr(d_group_sums)), ctx)
+
+
+def wl_per_loop(ctx, ens, fld, rho, T, spin, precision, loop0, n_loops):
+    """Per-loop (phase, spin exponent, w), each (n_loops, n_rho, n_T)."""
+    rho = _host_f64(rho)
+    T = _host_f64(T)
+    shape = (n_loops, rho.size, T.size)
+    ph, sp, w = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    _check(_lib.wl_per_loop(ctx, ens, ctypes.byref(fld), _ptr(rho), rho.size,
+                            _ptr(T), T.size, int(spin), int(precision),
+                            int(loop0), int(n_loops), _ptr(ph), _ptr(sp),
+                            _ptr(w)), ctx)
+    return ph, sp, w
+
+
+def wl_set_timing(ctx, enable=True):
+    _check(_lib.wl_set_timing(ctx, int(bool(enable))), ctx)
+
+
+def wl_last_kernel_ms(ctx):
+    ms = _d()
+    _check(_lib.wl_last_kernel_ms(ctx, ctypes.byref(ms)), ctx)
+    return ms.value
+
+
+def wl_kernel_ms_total(ctx):
+    """(sum of recorded main-kernel durations in ms, number of launches)."""
+    ms = _d()
+    n = _i64()
+    _check(_lib.wl_kernel_ms_total(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def raw_function(name):
+    """The ctypes function object of an exported symbol."""
+    return getattr(_lib, name)

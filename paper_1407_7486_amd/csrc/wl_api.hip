@@ -1,0 +1,545 @@
+// Host side of the C ABI declared in include/wl.h: argument checks, device
+// buffers, work decomposition and the launches (kernels in wl_kernels.hip).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/wl.h"
+#include "wl_internal.h"
+
+struct wl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  std::string err;
+  // scratch reused across calls (grown on demand, freed by wl_destroy)
+  void* d_grid = nullptr;
+  size_t grid_bytes = 0;
+  void* d_out = nullptr;
+  size_t out_bytes = 0;
+  void* d_partial = nullptr;
+  size_t partial_bytes = 0;
+  int* d_flag = nullptr;
+  // timing of the main kernel: one event pair per launch since timing was
+  // enabled (pairs are pooled and reused)
+  bool timing = false;
+  size_t n_timed = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+struct wl_ens {
+  wl_ctx* ctx = nullptr;
+  int64_t n_loops = 0;
+  int32_t n_ppl = 0;
+  int32_t n_groups = 0;
+  float* d_x = nullptr;
+  float* d_y = nullptr;
+  float4* d_seg = nullptr;
+};
+
+namespace {
+
+int fail(wl_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(wl_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, WL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the context's device current for the duration of a call and
+// restores the caller's device afterwards.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t status = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    status = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int ensure(wl_ctx* ctx, void** p, size_t* have, size_t need, const char* what) {
+  if (need <= *have) return WL_OK;
+  if (*p) {
+    // pending work may still read the old buffer
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(p, need);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, WL_ENOMEM, "hipMalloc(%zu bytes) for %s failed", need, what);
+  }
+  *have = need;
+  return WL_OK;
+}
+
+int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
+  if (!f) return fail(ctx, WL_EINVAL, "field is NULL");
+  if (f->kind < WL_CONST || f->kind > WL_RATIONAL)
+    return fail(ctx, WL_EINVAL, "unknown field kind %d", f->kind);
+  if (f->reserved != 0) return fail(ctx, WL_EINVAL, "field.reserved must be 0");
+  if (!isfinite(f->eB0)) return fail(ctx, WL_EINVAL, "field.eB0 not finite");
+  const double lam = f->lambda;
+  if (f->kind != WL_CONST && !(isfinite(lam) && lam > 0.0))
+    return fail(ctx, WL_EINVAL, "field.lambda must be finite and > 0");
+  const double l = (f->kind == WL_CONST) ? 1.0 : lam;
+  const double log2e = 1.4426950408889634074;
+  a->kind = f->kind;
+  a->inv_lam_d = 1.0 / l;
+  a->inv_lam2_d = 1.0 / (l * l);
+  a->lam2_d = l * l;
+  a->inv_lam = (float)a->inv_lam_d;
+  a->inv_lam2 = (float)a->inv_lam2_d;
+  a->lam2 = (float)a->lam2_d;
+  a->exp2_scale = 0.0f;
+  switch (f->kind) {
+    case WL_CONST:  // g = eB0/2, b = eB0
+      a->cphi = 0.5 * f->eB0;
+      a->cspin = f->eB0;
+      break;
+    case WL_SECH2:  // g = eB0 q(u), b = eB0 sech^2 = eB0 * 4 * E/(1+E)^2
+      a->exp2_scale = (float)(-2.0 * log2e / l);
+      a->cphi = f->eB0;
+      a->cspin = 4.0 * f->eB0;
+      break;
+    case WL_GAUSS:  // g = (eB0/2) (1-E)/v, b = eB0 E
+      a->exp2_scale = (float)(-log2e / (l * l));
+      a->cphi = 0.5 * f->eB0;
+      a->cspin = f->eB0;
+      break;
+    case WL_RATIONAL:  // g = (eB0 lam^2/2) r, b = eB0 lam^4 r^2
+      a->cphi = 0.5 * f->eB0 * l * l;
+      a->cspin = f->eB0 * l * l * l * l;
+      break;
+  }
+  return WL_OK;
+}
+
+int check_grid(wl_ctx* ctx, const double* rho, int32_t n_rho, const double* T,
+               int32_t n_T) {
+  if (n_rho < 0 || n_T < 0) return fail(ctx, WL_EINVAL, "negative grid size");
+  if ((int64_t)n_rho * n_T > (int64_t)INT32_MAX)
+    return fail(ctx, WL_EINVAL, "grid has more than 2^31-1 points");
+  if ((n_rho > 0 && !rho) || (n_T > 0 && !T))
+    return fail(ctx, WL_EINVAL, "grid pointer is NULL");
+  for (int32_t j = 0; j < n_rho; ++j)
+    if (!(isfinite(rho[j]) && rho[j] >= 0.0))
+      return fail(ctx, WL_EINVAL, "rho[%d] must be finite and >= 0", j);
+  for (int32_t k = 0; k < n_T; ++k)
+    if (!(isfinite(T[k]) && T[k] > 0.0))
+      return fail(ctx, WL_EINVAL, "T[%d] must be finite and > 0", k);
+  return WL_OK;
+}
+
+int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision) {
+  if (!ens) return fail(ctx, WL_EINVAL, "ensemble is NULL");
+  if (ens->ctx != ctx) return fail(ctx, WL_EINVAL, "ensemble belongs to another context");
+  if (spin != 0 && spin != 1) return fail(ctx, WL_EINVAL, "spin must be 0 or 1");
+  if (precision < WL_FP32C || precision > WL_FP64)
+    return fail(ctx, WL_EINVAL, "unknown precision %d", precision);
+  return WL_OK;
+}
+
+wl::Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts) {
+  wl::Sched s{};
+  s.loops_per_group = e->n_loops / e->n_groups;
+  s.n_chunks = (n_pts + wl::kWave - 1) / wl::kWave;
+  // Enough wavefronts for ~8 per SIMD (4 SIMDs per CU) so that the equal-
+  // cost items keep every SIMD busy until the end; split each group's loops
+  // into sub-ranges when groups x chunks alone fall short.
+  const int64_t target = (int64_t)ctx->num_cu * 4 * 8;
+  const int64_t base = (int64_t)e->n_groups * s.n_chunks;
+  int64_t n_sub = (target + base - 1) / base;
+  if (n_sub < 1) n_sub = 1;
+  if (n_sub > s.loops_per_group) n_sub = s.loops_per_group;
+  s.loops_per_sub = (s.loops_per_group + n_sub - 1) / n_sub;
+  // no empty sub-ranges
+  n_sub = (s.loops_per_group + s.loops_per_sub - 1) / s.loops_per_sub;
+  s.n_sub = (int32_t)n_sub;
+  s.n_items = base * n_sub;
+  s.n_wg = (int32_t)((s.n_items + wl::kWavesPerWG - 1) / wl::kWavesPerWG);
+  s.n_xcd = 8;  // MI355X: 8 XCDs; workgroups are dealt round-robin
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wl_version(void) { return "wl 0.1 (gfx950)"; }
+
+const char* wl_strerror(int code) {
+  switch (code) {
+    case WL_OK: return "ok";
+    case WL_EINVAL: return "invalid argument";
+    case WL_ENOMEM: return "out of memory";
+    case WL_EHIP: return "HIP runtime error";
+    case WL_ENODEV: return "no usable gfx950 device";
+  }
+  return "unknown error code";
+}
+
+const char* wl_last_error(const wl_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int wl_create(wl_ctx** out, int device, void* hip_stream) {
+  if (!out) return WL_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return WL_ENODEV;
+  }
+  if (device < 0 || device >= n) return WL_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return WL_ENODEV;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return WL_ENODEV;
+  wl_ctx* c = new (std::nothrow) wl_ctx();
+  if (!c) return WL_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->num_cu = prop.multiProcessorCount;
+  DeviceGuard g(device);
+  if (g.status != hipSuccess || hipMalloc((void**)&c->d_flag, sizeof(int)) != hipSuccess) {
+    wl_destroy(c);
+    return WL_ENOMEM;
+  }
+  *out = c;
+  return WL_OK;
+}
+
+int wl_destroy(wl_ctx* ctx) {
+  if (!ctx) return WL_OK;
+  {
+    DeviceGuard g(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->d_grid) (void)hipFree(ctx->d_grid);
+    if (ctx->d_out) (void)hipFree(ctx->d_out);
+    if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+    if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    for (auto& pr : ctx->events) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  }
+  delete ctx;
+  return WL_OK;
+}
+
+int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
+                       int64_t n_loops, int32_t n_ppl, int32_t n_groups,
+                       int32_t flags, wl_ens** out) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, WL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!y_x || !y_y) return fail(ctx, WL_EINVAL, "coordinate pointer is NULL");
+  if (n_loops < 1) return fail(ctx, WL_EINVAL, "n_loops must be >= 1");
+  if (n_ppl < 2) return fail(ctx, WL_EINVAL, "n_ppl must be >= 2");
+  if (n_groups < 1 || n_loops % n_groups != 0)
+    return fail(ctx, WL_EINVAL, "n_groups must be >= 1 and divide n_loops");
+  if (flags != WL_HOST_PTR && flags != WL_DEVICE_PTR)
+    return fail(ctx, WL_EINVAL, "unknown flags %d", flags);
+  if (n_loops > ((int64_t)1 << 40) / n_ppl)
+    return fail(ctx, WL_EINVAL, "ensemble too large");
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const int64_t npts = n_loops * n_ppl;
+  wl_ens* e = new (std::nothrow) wl_ens();
+  if (!e) return fail(ctx, WL_ENOMEM, "host allocation failed");
+  e->ctx = ctx;
+  e->n_loops = n_loops;
+  e->n_ppl = n_ppl;
+  e->n_groups = n_groups;
+  auto cleanup = [&](int code) {
+    if (e->d_x) (void)hipFree(e->d_x);
+    if (e->d_y) (void)hipFree(e->d_y);
+    if (e->d_seg) (void)hipFree(e->d_seg);
+    delete e;
+    return code;
+  };
+  if (hipMalloc((void**)&e->d_x, npts * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&e->d_y, npts * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess) {
+    (void)hipGetLastError();
+    return cleanup(fail(ctx, WL_ENOMEM, "device allocation of %lld points failed",
+                        (long long)npts));
+  }
+  const hipMemcpyKind kind =
+      flags == WL_DEVICE_PTR ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t err = hipMemcpyAsync(e->d_x, y_x, npts * sizeof(float), kind, ctx->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->d_y, y_y, npts * sizeof(float), kind, ctx->stream);
+  if (err == hipSuccess) err = hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream);
+  if (err == hipSuccess)
+    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, ctx->d_flag, ctx->stream);
+  int bad = 0;
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(&bad, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+  if (err != hipSuccess) return cleanup(hip_fail(ctx, err, "ensemble upload"));
+  if (bad) return cleanup(fail(ctx, WL_EINVAL, "non-finite loop coordinate"));
+  *out = e;
+  return WL_OK;
+}
+
+int wl_ensemble_free(wl_ens* ens) {
+  if (!ens) return WL_OK;
+  DeviceGuard g(ens->ctx->device);
+  if (ens->ctx->stream) (void)hipStreamSynchronize(ens->ctx->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipFree(ens->d_x);
+  (void)hipFree(ens->d_y);
+  (void)hipFree(ens->d_seg);
+  delete ens;
+  return WL_OK;
+}
+
+int wl_ensemble_info(const wl_ens* ens, int64_t* n_loops, int32_t* n_ppl,
+                     int32_t* n_groups) {
+  if (!ens) return WL_EINVAL;
+  if (n_loops) *n_loops = ens->n_loops;
+  if (n_ppl) *n_ppl = ens->n_ppl;
+  if (n_groups) *n_groups = ens->n_groups;
+  return WL_OK;
+}
+
+int wl_set_timing(wl_ctx* ctx, int32_t enable) {
+  if (!ctx) return WL_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->n_timed = 0;
+  return WL_OK;
+}
+
+static int elapsed(wl_ctx* ctx, size_t i, double* ms) {
+  hipError_t e = hipEventSynchronize(ctx->events[i].second);
+  float f = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, ctx->events[i].first, ctx->events[i].second);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+  *ms = f;
+  return WL_OK;
+}
+
+int wl_last_kernel_ms(wl_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return WL_EINVAL;
+  ctx->err.clear();
+  if (ctx->n_timed == 0) return fail(ctx, WL_EINVAL, "no timed launch recorded");
+  DeviceGuard g(ctx->device);
+  return elapsed(ctx, ctx->n_timed - 1, ms);
+}
+
+int wl_kernel_ms_total(wl_ctx* ctx, double* total_ms, int64_t* count) {
+  if (!ctx || !total_ms || !count) return WL_EINVAL;
+  ctx->err.clear();
+  if (ctx->n_timed == 0) return fail(ctx, WL_EINVAL, "no timed launch recorded");
+  DeviceGuard g(ctx->device);
+  double tot = 0.0;
+  for (size_t i = 0; i < ctx->n_timed; ++i) {
+    double ms;
+    int rc = elapsed(ctx, i, &ms);
+    if (rc) return rc;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = (int64_t)ctx->n_timed;
+  return WL_OK;
+}
+
+// Event pair for the next timed launch (created on first use).
+static hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
+  if (ctx->n_timed == ctx->events.size()) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return e;
+    }
+    ctx->events.emplace_back(e0, e1);
+  }
+  *a = ctx->events[ctx->n_timed].first;
+  *b = ctx->events[ctx->n_timed].second;
+  return hipSuccess;
+}
+
+// Enqueue one evaluation; grid and outputs are device memory.
+static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
+                          const double* d_rho, int32_t n_rho, const double* d_T,
+                          int32_t n_T, int32_t spin, int32_t precision,
+                          double* d_mean, double* d_err, double* d_sums) {
+  const int32_t n_pts = n_rho * n_T;
+  const wl::Sched s = make_sched(ctx, ens, n_pts);
+  double* main_out = d_sums;
+  if (s.n_sub > 1) {
+    const size_t need = (size_t)ens->n_groups * s.n_sub * n_pts * sizeof(double);
+    int rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "partial sums");
+    if (rc) return rc;
+    main_out = (double*)ctx->d_partial;
+  }
+  hipError_t e = hipSuccess;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (ctx->timing) {
+    e = next_events(ctx, &ev0, &ev1);
+    if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
+  }
+  if (e == hipSuccess)
+    e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_x, ens->d_y,
+                           ens->n_ppl, d_rho, d_T, n_T, n_pts, s, main_out,
+                           ctx->stream);
+  if (e == hipSuccess && ctx->timing) {
+    e = hipEventRecord(ev1, ctx->stream);
+    if (e == hipSuccess) ctx->n_timed++;
+  }
+  if (e == hipSuccess && s.n_sub > 1)
+    e = wl::launch_reduce_sub(main_out, ens->n_groups, s.n_sub, n_pts, d_sums, ctx->stream);
+  if (e == hipSuccess && (d_mean || d_err))
+    e = wl::launch_stats(d_sums, ens->n_groups, n_pts, ens->n_loops, d_mean, d_err,
+                         ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
+  return WL_OK;
+}
+
+int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                     const double* d_rho, int32_t n_rho, const double* d_T,
+                     int32_t n_T, int32_t spin, int32_t precision,
+                     double* d_mean, double* d_err, double* d_group_sums) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  int rc = check_common(ctx, ens, spin, precision);
+  if (rc) return rc;
+  wl::FieldArgs fa;
+  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if (n_rho < 0 || n_T < 0) return fail(ctx, WL_EINVAL, "negative grid size");
+  if ((int64_t)n_rho * n_T > (int64_t)INT32_MAX)
+    return fail(ctx, WL_EINVAL, "grid has more than 2^31-1 points");
+  if ((int64_t)n_rho * n_T == 0) return WL_OK;
+  if (!d_rho || !d_T || !d_group_sums)
+    return fail(ctx, WL_EINVAL, "device pointer is NULL");
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  return average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
+                        d_err, d_group_sums);
+}
+
+int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+               const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+               int32_t spin, int32_t precision, double* mean, double* err,
+               double* group_sums) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  int rc = check_common(ctx, ens, spin, precision);
+  if (rc) return rc;
+  wl::FieldArgs fa;
+  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
+  const int64_t n_pts = (int64_t)n_rho * n_T;
+  if (n_pts == 0) return WL_OK;
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
+  const size_t sums_n = (size_t)ens->n_groups * n_pts;
+  const size_t obytes = (sums_n + 2 * (size_t)n_pts) * sizeof(double);
+  if ((rc = ensure(ctx, &ctx->d_grid, &ctx->grid_bytes, gbytes, "grid"))) return rc;
+  if ((rc = ensure(ctx, &ctx->d_out, &ctx->out_bytes, obytes, "results"))) return rc;
+  double* d_rho = (double*)ctx->d_grid;
+  double* d_T = d_rho + n_rho;
+  double* d_sums = (double*)ctx->d_out;
+  double* d_mean = d_sums + sums_n;
+  double* d_err = d_mean + n_pts;
+  hipError_t e = hipMemcpyAsync(d_rho, rho, n_rho * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "grid upload");
+  if ((rc = average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
+                           d_err, d_sums)))
+    return rc;
+  if (group_sums)
+    e = hipMemcpyAsync(group_sums, d_sums, sums_n * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && mean)
+    e = hipMemcpyAsync(mean, d_mean, n_pts * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && err)
+    e = hipMemcpyAsync(err, d_err, n_pts * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "wl_average");
+  return WL_OK;
+}
+
+int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                int32_t spin, int32_t precision, int64_t loop0, int64_t n_loops,
+                double* phase, double* spin_exp, double* w) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  int rc = check_common(ctx, ens, spin, precision);
+  if (rc) return rc;
+  wl::FieldArgs fa;
+  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
+  if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
+    return fail(ctx, WL_EINVAL, "loop range [%lld, %lld) outside the ensemble",
+                (long long)loop0, (long long)(loop0 + n_loops));
+  const int64_t n_pts = (int64_t)n_rho * n_T;
+  if (n_pts == 0 || n_loops == 0) return WL_OK;
+  if (n_loops * n_pts > ((int64_t)1 << 27))
+    return fail(ctx, WL_EINVAL, "n_loops * grid points above 2^27 in one call");
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
+  const size_t each = (size_t)(n_loops * n_pts);
+  if ((rc = ensure(ctx, &ctx->d_grid, &ctx->grid_bytes, gbytes, "grid"))) return rc;
+  if ((rc = ensure(ctx, &ctx->d_out, &ctx->out_bytes, 3 * each * sizeof(double),
+                   "per-loop results")))
+    return rc;
+  double* d_rho = (double*)ctx->d_grid;
+  double* d_T = d_rho + n_rho;
+  double* d_ph = (double*)ctx->d_out;
+  double* d_sp = d_ph + each;
+  double* d_w = d_sp + each;
+  hipError_t e = hipMemcpyAsync(d_rho, rho, n_rho * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = wl::launch_per_loop(precision, spin, fa, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl,
+                            d_rho, d_T, n_T, (int32_t)n_pts, loop0, n_loops, d_ph, d_sp, d_w,
+                            ctx->stream);
+  if (e == hipSuccess && phase)
+    e = hipMemcpyAsync(phase, d_ph, each * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess && spin_exp)
+    e = hipMemcpyAsync(spin_exp, d_sp, each * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && w)
+    e = hipMemcpyAsync(w, d_w, each * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "wl_per_loop");
+  return WL_OK;
+}
+
+}  // extern "C"

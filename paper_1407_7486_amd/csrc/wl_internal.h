@@ -1,0 +1,78 @@
+// Internal declarations shared by the host API (wl_api.hip) and the kernels
+// (wl_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wl {
+
+// Per-segment unit-loop quantities used by the FP32 kernels, one float4 per
+// segment i -> i+1 of a unit loop y (indices mod N):
+//   x = m_x        = (y_i^x + y_{i+1}^x)/2       unit midpoint, x
+//   y = |m|^2      = m_x^2 + m_y^2
+//   z = d_y        = y_{i+1}^y - y_i^y           unit step, y
+//   w = c          = y_i^x y_{i+1}^y - y_i^y y_{i+1}^x   unit cross product
+// so that for the scaled, shifted loop (rho_cm + s y^x, s y^y), s = sqrt(T):
+//   rho^2(midpoint) = rho^2 + 2 rho s m_x + T |m|^2
+//   cross_i         = rho s d_y + T c.
+
+// Work decomposition of one evaluation: one wavefront per item
+// (group g, loop sub-range `sub`, chunk of 64 grid points).
+struct Sched {
+  int64_t loops_per_group;  // N_l / G
+  int64_t loops_per_sub;    // ceil(loops_per_group / n_sub)
+  int32_t n_sub;            // sub-ranges per group
+  int32_t n_chunks;         // ceil(n_pts / 64)
+  int64_t n_items;          // G * n_sub * n_chunks
+  int32_t n_wg;             // ceil(n_items / waves per workgroup)
+  int32_t n_xcd;            // XCDs the dispatcher round-robins over
+};
+
+// Field constants prepared on the host for one launch.
+struct FieldArgs {
+  int32_t kind;
+  // FP32 path
+  float inv_lam;     // 1/lambda
+  float inv_lam2;    // 1/lambda^2
+  float lam2;        // lambda^2
+  float exp2_scale;  // SECH2: -2 log2(e)/lambda ; GAUSS: -log2(e)/lambda^2
+  // FP64 path
+  double inv_lam_d, inv_lam2_d, lam2_d;
+  // epilogue: Phi = cphi * sum_i cross_i qa_i ; S = cspin (T/N) sum_i qb_i
+  double cphi, cspin;
+};
+
+constexpr int kWavesPerWG = 4;
+constexpr int kWave = 64;
+
+// Launchers (wl_kernels.hip).  All enqueue on `stream` and return the HIP
+// launch status.
+hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
+                       int32_t n_ppl, float4* d_seg, int* d_bad,
+                       hipStream_t stream);
+
+hipError_t launch_average(int precision, int spin, const FieldArgs& f,
+                          const float4* d_seg, const float* d_x,
+                          const float* d_y, int32_t n_ppl,
+                          const double* d_rho, const double* d_T, int32_t n_T,
+                          int32_t n_pts, const Sched& s, double* d_out,
+                          hipStream_t stream);
+
+hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
+                           const float4* d_seg, const float* d_x,
+                           const float* d_y, int32_t n_ppl,
+                           const double* d_rho, const double* d_T,
+                           int32_t n_T, int32_t n_pts, int64_t loop0,
+                           int64_t n_loops, double* d_phase, double* d_spin,
+                           double* d_w, hipStream_t stream);
+
+hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,
+                             int32_t n_sub, int32_t n_pts, double* d_sums,
+                             hipStream_t stream);
+
+hipError_t launch_stats(const double* d_sums, int32_t n_groups, int32_t n_pts,
+                        int64_t n_loops, double* d_mean, double* d_err,
+                        hipStream_t stream);
+
+}  // namespace wl

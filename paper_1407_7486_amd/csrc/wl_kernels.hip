@@ -1,0 +1,512 @@
+// Wilson-loop ensemble average: HIP kernels for gfx950 (MI355X).
+//
+// Mapping.  One wavefront owns one work item = (loop group g, sub-range of
+// the group's loops, 64 consecutive (rho_cm, T) grid points).  Lane j holds
+// grid point j of the chunk and walks every segment of every loop of the
+// item in order.  The segment data of the loop being walked are the same
+// for all 64 lanes, so they arrive through wave-uniform (scalar) loads and
+// sit in SGPRs: one fetch of a segment serves 64 (rho, T) evaluations, and
+// the loop tile is reused across the whole grid without any cross-lane
+// traffic.  A lane's per-loop phase and spin sums therefore need no
+// wavefront reduction, and its FP64 group-sum accumulator has exactly one
+// owner and a fixed loop order (deterministic results).
+//
+// Arithmetic per segment (Sec. 3.2.1, Eqs. rhoi..Ci with the midpoint rule
+// t = 1/2, and Sec. 3.2.2, Eq. Wfermfpl):
+//   rho^2 = P + Q m_x + R |m|^2,   cross = U d_y + R c
+//   (P = rho_cm^2, Q = 2 rho_cm s, R = s^2 = T, U = rho_cm s, s = sqrt(T))
+//   phase += cross * qa(rho^2),  spin += qb(rho^2)
+// with qa, qb the field's phase weight and field strength up to constants
+// that the FP64 epilogue applies once per loop:
+//   Phi = cphi * sum cross qa,   S = cspin (T/N) sum qb,
+//   w = cos(Phi) * cosh(S).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "wl_internal.h"
+#include "wl_poly.h"
+
+namespace wl {
+namespace {
+
+constexpr float kLn2f = 0.69314718055994531f;
+constexpr double kLn2 = 0.69314718055994530942;
+
+enum { kConst = 0, kSech2 = 1, kGauss = 2, kRational = 3 };
+
+// ----------------------------------------------------------- FP32 fields
+template <int DEG>
+__device__ __forceinline__ float horner_f32(const float (&c)[DEG + 1], float v) {
+  float acc = c[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) acc = fmaf(acc, v, c[k]);
+  return acc;
+}
+
+template <int DEG>
+__device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double v) {
+  double acc = c[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) acc = fma(acc, v, c[k]);
+  return acc;
+}
+
+// qa: phase weight, qb: spin integrand, as functions of rho^2 (FP32,
+// hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
+template <int KIND>
+__device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
+                                          float& qa, float& qb) {
+  if constexpr (KIND == kConst) {
+    (void)r2;
+    (void)f;
+    qa = 1.0f;
+    qb = 1.0f;
+  } else if constexpr (KIND == kSech2) {
+    // u = rho/lambda, E = exp(-2u).  sech^2 u = 4 E/(1+E)^2 (4 in cspin).
+    // g/eB0 = (u tanh u - ln cosh u)/u^2 = (ln2 - ln(1+E) - 2uE/(1+E))/u^2;
+    // below u = 1 that difference cancels, so a polynomial in u^2 is used.
+    r2 = fmaxf(r2, 1e-30f);
+    const float rs = __builtin_amdgcn_rsqf(r2);  // 1/rho
+    const float rho = r2 * rs;
+    const float E = __builtin_amdgcn_exp2f(rho * f.exp2_scale);
+    const float opE = 1.0f + E;
+    const float ip = __builtin_amdgcn_rcpf(opE);
+    const float Eip = E * ip;
+    qb = Eip * ip;
+    const float v = r2 * f.inv_lam2;
+    if (v < 1.0f) {
+      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v);
+    } else {
+      const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
+      const float u = rho * f.inv_lam;
+      const float h = fmaf(-kLn2f, lg, kLn2f) - 2.0f * u * Eip;
+      qa = h * (rs * rs) * f.lam2;
+    }
+  } else if constexpr (KIND == kGauss) {
+    // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
+    // below v = 1/2 where 1-E cancels); b/eB0 = E.
+    r2 = fmaxf(r2, 0.0f);
+    const float v = r2 * f.inv_lam2;
+    const float E = __builtin_amdgcn_exp2f(r2 * f.exp2_scale);
+    qb = E;
+    if (v < 0.5f) {
+      qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v);
+    } else {
+      qa = (1.0f - E) * __builtin_amdgcn_rcpf(v);
+    }
+  } else {  // kRational: r = 1/(lambda^2 + rho^2); g ~ r, b ~ r^2
+    const float r = __builtin_amdgcn_rcpf(fmaxf(r2, 0.0f) + f.lam2);
+    qa = r;
+    qb = r * r;
+  }
+}
+
+// ----------------------------------------------------------- FP64 fields
+template <int KIND>
+__device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
+                                          double& qa, double& qb) {
+  if constexpr (KIND == kConst) {
+    (void)r2;
+    (void)f;
+    qa = 1.0;
+    qb = 1.0;
+  } else if constexpr (KIND == kSech2) {
+    const double u = sqrt(r2) * f.inv_lam_d;
+    const double E = exp(-2.0 * u);
+    const double ip = 1.0 / (1.0 + E);
+    const double Eip = E * ip;
+    qb = Eip * ip;
+    const double v = r2 * f.inv_lam2_d;
+    if (v < 0.25) {
+      qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v);
+    } else {
+      qa = (kLn2 - log1p(E) - 2.0 * u * Eip) / v;
+    }
+  } else if constexpr (KIND == kGauss) {
+    const double v = r2 * f.inv_lam2_d;
+    qb = exp(-v);
+    qa = v > 0.0 ? -expm1(-v) / v : 1.0;
+  } else {
+    const double r = 1.0 / (r2 + f.lam2_d);
+    qa = r;
+    qb = r * r;
+  }
+}
+
+// --------------------------------------------------- compensated sums
+__device__ __forceinline__ void kahan_fma(float& s, float& c, float a, float b) {
+  const float y = fmaf(a, b, -c);
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float a) {
+  const float y = a - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+struct LaneF32 {
+  float P, Q, R, U;  // rho^2, 2 rho s, s^2, rho s
+};
+
+// Phase and spin sums of one loop for this lane's grid point (FP32 path).
+// `seg` is wave-uniform.  Returns sum cross*qa and sum qb in FP64.
+template <int KIND, bool SPIN, bool COMP>
+__device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
+                                              int32_t n, const LaneF32& c,
+                                              const FieldArgs& f, double& A,
+                                              double& B) {
+  constexpr bool kSpinSum = SPIN && KIND != kConst;
+  float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
+  auto step = [&](const float4 s) {
+    const float r2 = fmaf(c.R, s.y, fmaf(c.Q, s.x, c.P));
+    const float cr = fmaf(c.R, s.w, c.U * s.z);
+    float qa, qb;
+    field_f32<KIND>(r2, f, qa, qb);
+    if constexpr (COMP) {
+      kahan_fma(as, ac, cr, qa);
+      if constexpr (kSpinSum) kahan_add(bs, bc, qb);
+    } else {
+      as = fmaf(cr, qa, as);
+      if constexpr (kSpinSum) bs += qb;
+    }
+  };
+  int32_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    // fetch the block's 8 segments up front so that one wait covers them
+    float4 sv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) step(sv[k]);
+  }
+  for (; i < n; ++i) step(seg[i]);
+  A = (double)as - (double)ac;
+  B = kSpinSum ? (double)bs - (double)bc : (double)n;
+}
+
+// FP64 path: reads the raw FP32 unit coordinates (exact in FP64) and forms
+// the midpoint, step and cross product of every segment in FP64.
+template <int KIND, bool SPIN>
+__device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
+                                              const float* __restrict__ Y,
+                                              int32_t n, double rho, double s,
+                                              const FieldArgs& f, double& A,
+                                              double& B) {
+  constexpr bool kSpinSum = SPIN && KIND != kConst;
+  double a = 0.0, b = 0.0;
+  auto step = [&](float x0f, float y0f, float x1f, float y1f) {
+    const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
+    const double mx = fma(s, 0.5 * (x0 + x1), rho);
+    const double my = s * (0.5 * (y0 + y1));
+    const double dx = s * (x1 - x0), dy = s * (y1 - y0);
+    const double cr = mx * dy - my * dx;
+    const double r2 = mx * mx + my * my;
+    double qa, qb;
+    field_f64<KIND>(r2, f, qa, qb);
+    a = fma(cr, qa, a);
+    if constexpr (kSpinSum) b += qb;
+  };
+  float xp = X[0], yp = Y[0];
+  int32_t i = 1;
+  for (; i + 4 <= n; i += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float xn = X[i + k], yn = Y[i + k];
+      step(xp, yp, xn, yn);
+      xp = xn;
+      yp = yn;
+    }
+  }
+  for (; i < n; ++i) {
+    const float xn = X[i], yn = Y[i];
+    step(xp, yp, xn, yn);
+    xp = xn;
+    yp = yn;
+  }
+  step(xp, yp, X[0], Y[0]);  // closing segment N-1 -> 0
+  A = a;
+  B = kSpinSum ? b : (double)n;
+}
+
+// Per-loop epilogue in FP64: phase, spin exponent and w.
+template <bool SPIN>
+__device__ __forceinline__ double epilogue(double A, double B, double T,
+                                           int32_t n, const FieldArgs& f,
+                                           double& phi, double& S) {
+  phi = f.cphi * A;
+  S = SPIN ? f.cspin * (T / n) * B : 0.0;
+  const double cw = cos(phi);
+  return SPIN ? cw * cosh(S) : cw;
+}
+
+__device__ __forceinline__ int64_t remap_wg(int32_t w, int32_t n_wg, int32_t n_xcd) {
+  // Workgroups are dealt round-robin to the XCDs; give each XCD a
+  // contiguous range of logical workgroups so that the items sharing a
+  // loop group (same loops, other grid chunks) run under one L2.
+  if (n_xcd <= 1) return w;
+  const int32_t per = n_wg / n_xcd, rem = n_wg % n_xcd;
+  const int32_t xcd = w % n_xcd, idx = w / n_xcd;
+  return xcd < rem ? (int64_t)xcd * (per + 1) + idx
+                   : (int64_t)rem * (per + 1) + (int64_t)(xcd - rem) * per + idx;
+}
+
+// ------------------------------------------------------------- kernels
+template <int KIND, bool SPIN, int PREC>
+__global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
+    const float4* __restrict__ seg, const float* __restrict__ X,
+    const float* __restrict__ Y, int32_t n_ppl,
+    const double* __restrict__ rho_g, const double* __restrict__ T_g,
+    int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,
+    double* __restrict__ out) {
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t lane = threadIdx.x % kWave;
+  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * kWavesPerWG + wave;
+  if (item >= sc.n_items) return;
+  const int32_t chunk = (int32_t)(item % sc.n_chunks);
+  const int64_t gs = item / sc.n_chunks;  // g * n_sub + sub
+  const int64_t g = gs / sc.n_sub;
+  const int64_t sub = gs % sc.n_sub;
+  const int64_t l0 = g * sc.loops_per_group + sub * sc.loops_per_sub;
+  int64_t l1 = l0 + sc.loops_per_sub;
+  const int64_t gend = (g + 1) * sc.loops_per_group;
+  if (l1 > gend) l1 = gend;
+
+  const int32_t p = chunk * kWave + lane;
+  const bool valid = p < n_pts;
+  const int32_t pp = valid ? p : n_pts - 1;
+  const double rho = rho_g[pp / n_T];
+  const double T = T_g[pp % n_T];
+  const double s = sqrt(T);
+  LaneF32 c;
+  c.P = (float)(rho * rho);
+  c.Q = (float)(2.0 * rho * s);
+  c.R = (float)T;
+  c.U = (float)(rho * s);
+
+  double acc = 0.0;
+  for (int64_t l = l0; l < l1; ++l) {
+    double A, B, phi, S;
+    if constexpr (PREC == 2) {
+      loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+    } else {
+      loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
+    }
+    acc += epilogue<SPIN>(A, B, T, n_ppl, f, phi, S);
+  }
+  if (valid) out[gs * n_pts + p] = acc;
+}
+
+template <int KIND, bool SPIN, int PREC>
+__global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
+    const float4* __restrict__ seg, const float* __restrict__ X,
+    const float* __restrict__ Y, int32_t n_ppl,
+    const double* __restrict__ rho_g, const double* __restrict__ T_g,
+    int32_t n_T, int32_t n_pts, int32_t n_chunks, FieldArgs f, int64_t loop0,
+    int64_t n_loops, double* __restrict__ o_phase, double* __restrict__ o_spin,
+    double* __restrict__ o_w) {
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t lane = threadIdx.x % kWave;
+  const int64_t item = (int64_t)blockIdx.x * kWavesPerWG + wave;
+  if (item >= n_loops * n_chunks) return;
+  const int64_t li = item / n_chunks;
+  const int32_t chunk = (int32_t)(item % n_chunks);
+  const int64_t l = loop0 + li;
+  const int32_t p = chunk * kWave + lane;
+  const bool valid = p < n_pts;
+  const int32_t pp = valid ? p : n_pts - 1;
+  const double rho = rho_g[pp / n_T];
+  const double T = T_g[pp % n_T];
+  const double s = sqrt(T);
+  LaneF32 c;
+  c.P = (float)(rho * rho);
+  c.Q = (float)(2.0 * rho * s);
+  c.R = (float)T;
+  c.U = (float)(rho * s);
+  double A, B, phi, S;
+  if constexpr (PREC == 2) {
+    loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+  } else {
+    loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
+  }
+  const double w = epilogue<SPIN>(A, B, T, n_ppl, f, phi, S);
+  if (valid) {
+    const int64_t o = li * n_pts + p;
+    o_phase[o] = phi;
+    o_spin[o] = S;
+    o_w[o] = w;
+  }
+}
+
+// Per-segment unit quantities (see wl_internal.h), formed in FP64 from the
+// FP32 coordinates and rounded once to FP32; flags non-finite input.
+__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
+                                              const float* __restrict__ Y,
+                                              int64_t n_loops, int32_t n_ppl,
+                                              float4* __restrict__ seg,
+                                              int* __restrict__ bad) {
+  const int64_t total = n_loops * n_ppl;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = t / n_ppl;
+    const int32_t i = (int32_t)(t % n_ppl);
+    const int32_t j = (i + 1 == n_ppl) ? 0 : i + 1;
+    const float x0f = X[l * n_ppl + i], y0f = Y[l * n_ppl + i];
+    const float x1f = X[l * n_ppl + j], y1f = Y[l * n_ppl + j];
+    if (!isfinite(x0f) || !isfinite(y0f)) *bad = 1;
+    const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
+    const double mx = 0.5 * (x0 + x1), my = 0.5 * (y0 + y1);
+    float4 o;
+    o.x = (float)mx;
+    o.y = (float)(mx * mx + my * my);
+    o.z = (float)(y1 - y0);
+    o.w = (float)(x0 * y1 - y0 * x1);
+    seg[t] = o;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sub(const double* __restrict__ part,
+                                                    int32_t n_groups, int32_t n_sub,
+                                                    int32_t n_pts,
+                                                    double* __restrict__ sums) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_groups * n_pts) return;
+  const int64_t g = t / n_pts, p = t % n_pts;
+  double acc = 0.0;
+  for (int32_t s = 0; s < n_sub; ++s) acc += part[(g * n_sub + s) * n_pts + p];
+  sums[t] = acc;
+}
+
+// Mean and standard error of the group means (Sec. 4.2.3) per grid point.
+__global__ __launch_bounds__(256) void k_stats(const double* __restrict__ sums,
+                                               int32_t n_groups, int32_t n_pts,
+                                               int64_t n_loops,
+                                               double* __restrict__ mean,
+                                               double* __restrict__ err) {
+  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pts) return;
+  double tot = 0.0;
+  for (int32_t g = 0; g < n_groups; ++g) tot += sums[(int64_t)g * n_pts + p];
+  const double m = tot / (double)n_loops;
+  const double per = (double)(n_loops / n_groups);
+  double ss = 0.0;
+  for (int32_t g = 0; g < n_groups; ++g) {
+    const double d = sums[(int64_t)g * n_pts + p] / per - m;
+    ss += d * d;
+  }
+  if (mean) mean[p] = m;
+  if (err) err[p] = n_groups > 1 ? sqrt(ss / ((double)n_groups * (n_groups - 1))) : NAN;
+}
+
+// ------------------------------------------------------------ dispatch
+template <int KIND, bool SPIN, int PREC>
+hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const float* X,
+                        const float* Y, int32_t n_ppl, const double* rho,
+                        const double* T, int32_t n_T, int32_t n_pts,
+                        const Sched& s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_average<KIND, SPIN, PREC>), dim3(s.n_wg),
+                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
+                     n_T, n_pts, f, s, out);
+  return hipGetLastError();
+}
+
+template <int KIND, bool SPIN, int PREC>
+hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const float* X,
+                       const float* Y, int32_t n_ppl, const double* rho,
+                       const double* T, int32_t n_T, int32_t n_pts,
+                       int64_t loop0, int64_t n_loops, double* ph, double* sp,
+                       double* w, hipStream_t st) {
+  const int32_t n_chunks = (n_pts + kWave - 1) / kWave;
+  const int64_t items = n_loops * n_chunks;
+  const int64_t n_wg = (items + kWavesPerWG - 1) / kWavesPerWG;
+  hipLaunchKernelGGL((k_per_loop<KIND, SPIN, PREC>), dim3((uint32_t)n_wg),
+                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
+                     n_T, n_pts, n_chunks, f, loop0, n_loops, ph, sp, w);
+  return hipGetLastError();
+}
+
+#define WL_DISPATCH(FN, ...)                                                    \
+  switch (f.kind * 6 + spin * 3 + precision) {                                  \
+    case 0: return FN<kConst, false, 0>(__VA_ARGS__);                           \
+    case 1: return FN<kConst, false, 1>(__VA_ARGS__);                           \
+    case 2: return FN<kConst, false, 2>(__VA_ARGS__);                           \
+    case 3: return FN<kConst, true, 0>(__VA_ARGS__);                            \
+    case 4: return FN<kConst, true, 1>(__VA_ARGS__);                            \
+    case 5: return FN<kConst, true, 2>(__VA_ARGS__);                            \
+    case 6: return FN<kSech2, false, 0>(__VA_ARGS__);                           \
+    case 7: return FN<kSech2, false, 1>(__VA_ARGS__);                           \
+    case 8: return FN<kSech2, false, 2>(__VA_ARGS__);                           \
+    case 9: return FN<kSech2, true, 0>(__VA_ARGS__);                            \
+    case 10: return FN<kSech2, true, 1>(__VA_ARGS__);                           \
+    case 11: return FN<kSech2, true, 2>(__VA_ARGS__);                           \
+    case 12: return FN<kGauss, false, 0>(__VA_ARGS__);                          \
+    case 13: return FN<kGauss, false, 1>(__VA_ARGS__);                          \
+    case 14: return FN<kGauss, false, 2>(__VA_ARGS__);                          \
+    case 15: return FN<kGauss, true, 0>(__VA_ARGS__);                           \
+    case 16: return FN<kGauss, true, 1>(__VA_ARGS__);                           \
+    case 17: return FN<kGauss, true, 2>(__VA_ARGS__);                           \
+    case 18: return FN<kRational, false, 0>(__VA_ARGS__);                       \
+    case 19: return FN<kRational, false, 1>(__VA_ARGS__);                       \
+    case 20: return FN<kRational, false, 2>(__VA_ARGS__);                       \
+    case 21: return FN<kRational, true, 0>(__VA_ARGS__);                        \
+    case 22: return FN<kRational, true, 1>(__VA_ARGS__);                        \
+    case 23: return FN<kRational, true, 2>(__VA_ARGS__);                        \
+    default: return hipErrorInvalidValue;                                       \
+  }
+
+}  // namespace
+
+hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
+                       int32_t n_ppl, float4* d_seg, int* d_bad,
+                       hipStream_t stream) {
+  const int64_t total = n_loops * n_ppl;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, d_x,
+                     d_y, n_loops, n_ppl, d_seg, d_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_average(int precision, int spin, const FieldArgs& f,
+                          const float4* d_seg, const float* d_x,
+                          const float* d_y, int32_t n_ppl, const double* d_rho,
+                          const double* d_T, int32_t n_T, int32_t n_pts,
+                          const Sched& s, double* d_out, hipStream_t stream) {
+  WL_DISPATCH(launch_avg_t, f, d_seg, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
+              s, d_out, stream)
+}
+
+hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
+                           const float4* d_seg, const float* d_x,
+                           const float* d_y, int32_t n_ppl,
+                           const double* d_rho, const double* d_T, int32_t n_T,
+                           int32_t n_pts, int64_t loop0, int64_t n_loops,
+                           double* d_phase, double* d_spin, double* d_w,
+                           hipStream_t stream) {
+  WL_DISPATCH(launch_pl_t, f, d_seg, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
+              loop0, n_loops, d_phase, d_spin, d_w, stream)
+}
+
+hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,
+                             int32_t n_sub, int32_t n_pts, double* d_sums,
+                             hipStream_t stream) {
+  const int64_t total = (int64_t)n_groups * n_pts;
+  hipLaunchKernelGGL(k_reduce_sub, dim3((uint32_t)((total + 255) / 256)),
+                     dim3(256), 0, stream, d_partial, n_groups, n_sub, n_pts,
+                     d_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const double* d_sums, int32_t n_groups, int32_t n_pts,
+                        int64_t n_loops, double* d_mean, double* d_err,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(k_stats, dim3((uint32_t)((n_pts + 255) / 256)), dim3(256),
+                     0, stream, d_sums, n_groups, n_pts, n_loops, d_mean, d_err);
+  return hipGetLastError();
+}
+
+}  // namespace wl

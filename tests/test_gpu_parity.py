@@ -1,0 +1,229 @@
+"""GPU path vs the FP64 oracle, through the C ABI (libwl.so).
+
+Every case prints its name before it touches the GPU.  Inputs come from the
+seeded generator (wlinputs); expected values only from the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import wlinputs
+from wl_tol import check_means, check_per_loop
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = {
+    "const": (0, 0.9, 1.0),
+    "sech2": (1, 1.3, 0.7),
+    "gauss": (2, 2.0, 0.9),
+    "rational": (3, 1.5, 0.8),
+}
+PRECS = {"fp32c": 0, "fp32": 1, "fp64": 2}
+RHO = np.array([0.0, 0.3, 1.1, 2.5, 5.0])
+TGRID = np.geomspace(1e-3, 30.0, 13)  # 65 grid points: one full chunk + 1
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wl():
+    import paper_1407_7486_amd as wl
+    return wl
+
+
+@pytest.fixture(scope="module")
+def ctx(wl):
+    c = wl.wl_create(0, None)
+    yield c
+    wl.wl_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def small(wl, ctx):
+    """128 ragged polygons of 203 points (203 % 8 = 3: unrolled blocks plus
+    a tail), 4 groups."""
+    x, y = wlinputs.polygon_loops(128, 203, seed=17)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 4)
+    yield x, y, ens
+    wl.wl_ensemble_free(ens)
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_eval(key, x, y, kind, eB0, lam, rho, T, spin, G):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.evaluate(x, y, kind, eB0, lam, rho, T, spin, G,
+                                             per_loop=True)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("fname", list(FIELDS))
+@pytest.mark.parametrize("spin", [0, 1])
+@pytest.mark.parametrize("pname", list(PRECS))
+def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
+    kind, eB0, lam = FIELDS[fname]
+    prec = PRECS[pname]
+    x, y, ens = small
+    say("small", fname, "spin", spin, pname)
+    o = oracle_eval((fname, spin), x, y, kind, eB0, lam, RHO, TGRID, spin, 4)
+    fld = wl.field(kind, eB0, lam)
+    ph, sp, w = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, 0, 128)
+    check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin)
+    mean, err, sums = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, prec)
+    o_mean, o_err, _ = oracle.stats(o["group_sums"], 128)
+    absw = np.abs(o["w"])
+    check_means(prec, mean, sums, o_mean, o["group_sums"], absw.mean(axis=0),
+                absw.reshape(4, 32, *absw.shape[1:]).sum(axis=1))
+    # the group error follows from the group sums the same way on both sides
+    _, e2, _ = oracle.stats(sums, 128)
+    np.testing.assert_allclose(err, e2, rtol=1e-9, atol=1e-300)
+
+
+def test_subrange_and_ragged_loop_window(wl, ctx, small):
+    """Per-loop evaluation of an interior window equals the matching rows of
+    a full evaluation (bit for bit: the same kernel arithmetic)."""
+    x, y, ens = small
+    say("window")
+    fld = wl.field(1, 1.3, 0.7)
+    full = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, 1, 0, 0, 128)
+    part = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, 1, 0, 37, 5)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[37:42], b)
+
+
+def test_deterministic(wl, ctx, small):
+    x, y, ens = small
+    say("determinism")
+    fld = wl.field(1, 1.3, 0.7)
+    a = wl.wl_average(ctx, ens, fld, RHO, TGRID, 1, 0)
+    b = wl.wl_average(ctx, ens, fld, RHO, TGRID, 1, 0)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v, equal_nan=True)
+
+
+def test_edge_cases(wl, ctx):
+    say("edge: empty grid, 2-point loops, one group, one loop")
+    x, y = wlinputs.polygon_loops(8, 2, seed=1)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 1)
+    try:
+        fld = wl.field(1, 1.0, 1.0)
+        m, e, s = wl.wl_average(ctx, ens, fld, np.zeros(0), TGRID, 1, 0)
+        assert m.size == 0
+        # a 2-point "loop" goes out and back: no enclosed flux, w = cosh S
+        ph, sp, w = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, 1, 2, 0, 8)
+        o = oracle.evaluate(x, y, 1, 1.0, 1.0, RHO, TGRID, 1, 1, per_loop=True)
+        assert np.abs(ph).max() < 1e-12
+        np.testing.assert_allclose(sp, o["spin"], rtol=1e-12, atol=1e-300)
+        m, e, s = wl.wl_average(ctx, ens, fld, RHO, TGRID, 1, 2)
+        assert np.isnan(e).all()  # a single group has no spread estimate
+        np.testing.assert_allclose(m, o["group_sums"][0] / 8, rtol=1e-12)
+    finally:
+        wl.wl_ensemble_free(ens)
+    x1, y1 = wlinputs.dloop_ensemble(1, 64, seed=3)
+    ens = wl.wl_ensemble_upload(ctx, x1, y1, 1)
+    try:
+        m, _, s = wl.wl_average(ctx, ens, wl.field(0, 1.0), RHO, TGRID, 0, 0)
+        o = oracle.evaluate(x1, y1, 0, 1.0, 1.0, RHO, TGRID, 0, 1)
+        np.testing.assert_allclose(m, o["group_sums"][0], atol=1e-6)
+    finally:
+        wl.wl_ensemble_free(ens)
+
+
+def test_invalid_arguments(wl, ctx):
+    say("invalid arguments")
+    x, y = wlinputs.dloop_ensemble(6, 16, seed=0)
+    with pytest.raises(wl.WLError) as ei:
+        wl.wl_ensemble_upload(ctx, x, y, 4)  # 6 % 4 != 0
+    assert ei.value.code == wl.WL_EINVAL
+    xb = x.copy()
+    xb[2, 5] = np.nan
+    with pytest.raises(wl.WLError) as ei:
+        wl.wl_ensemble_upload(ctx, xb, y, 3)
+    assert ei.value.code == wl.WL_EINVAL and "non-finite" in str(ei.value)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 3)
+    try:
+        for bad_T in ([0.0], [-1.0], [np.inf]):
+            with pytest.raises(wl.WLError):
+                wl.wl_average(ctx, ens, wl.field(1, 1.0, 1.0), RHO, bad_T, 0, 0)
+        with pytest.raises(wl.WLError):
+            wl.wl_average(ctx, ens, wl.field(1, 1.0, 1.0), [-0.5], TGRID, 0, 0)
+        with pytest.raises(wl.WLError):
+            wl.wl_average(ctx, ens, wl.field(1, 1.0, 0.0), RHO, TGRID, 0, 0)
+        with pytest.raises(wl.WLError):
+            wl.wl_average(ctx, ens, wl.field(7, 1.0, 1.0), RHO, TGRID, 0, 0)
+        with pytest.raises(wl.WLError):
+            wl.wl_average(ctx, ens, wl.field(1, 1.0, 1.0), RHO, TGRID, 2, 0)
+        with pytest.raises(wl.WLError):
+            wl.wl_average(ctx, ens, wl.field(1, 1.0, 1.0), RHO, TGRID, 0, 5)
+        with pytest.raises(wl.WLError):
+            wl.wl_per_loop(ctx, ens, wl.field(1, 1.0, 1.0), RHO, TGRID, 0, 0, 4, 3)
+    finally:
+        wl.wl_ensemble_free(ens)
+
+
+@pytest.mark.parametrize("spin", [0, 1])
+def test_constant_field_against_exact_average(wl, ctx, spin):
+    """End to end: the GPU mean over 16384 d-loops of 64 points matches the
+    exact finite-N constant-field average within 5 group errors."""
+    say("constant field exact, spin", spin)
+    x, y = wlinputs.dloop_ensemble(16384, 64, seed=2)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 64)
+    try:
+        T = np.array([0.3, 1.0, 2.0, 4.0])
+        rho = np.array([0.0, 2.0])
+        for prec in (0, 2):
+            m, e, _ = wl.wl_average(ctx, ens, wl.field(0, 1.0), rho, T, spin, prec)
+            want = oracle.w_scalar_finite_n(T, 64) * (np.cosh(T) if spin else 1.0)
+            assert np.all(np.abs(m - want) < 5 * e + 1e-9)
+    finally:
+        wl.wl_ensemble_free(ens)
+
+
+@pytest.fixture(scope="module")
+def big(wl, ctx):
+    """The throughput workload: 65536 d-loops of 4096 points, 64 groups."""
+    cfg = wlinputs.WORKLOADS["sech2_spinor_64k"]
+    x, y = wlinputs.dloop_ensemble(cfg["n_loops"], cfg["n_ppl"], seed=cfg["seed"])
+    ens = wl.wl_ensemble_upload(ctx, x, y, cfg["n_groups"])
+    yield cfg, x, y, ens
+    wl.wl_ensemble_free(ens)
+
+
+@pytest.mark.parametrize("pname", ["fp32c", "fp64"])
+def test_full_size_sampled(wl, ctx, big, pname):
+    """Full 65536 x 4096 ensemble on the full 64 x 64 grid, in the launch
+    configuration of the benchmark; group sums checked against the oracle at
+    sampled (group, rho, T) cells, per-loop values at sampled loops."""
+    cfg, x, y, ens = big
+    prec = PRECS[pname]
+    say("full size", pname)
+    rho = wlinputs.rho_grid(*cfg["rho"])
+    T = wlinputs.t_grid(*cfg["T"])
+    fld = wl.field(cfg["kind"], cfg["eB0"], cfg["lam"])
+    mean, err, sums = wl.wl_average(ctx, ens, fld, rho, T, 1, prec)
+    assert np.isfinite(mean).all() and np.isfinite(sums).all()
+    per = cfg["n_loops"] // cfg["n_groups"]
+    np.testing.assert_allclose(sums.sum(axis=0) / cfg["n_loops"], mean, rtol=1e-12,
+                               atol=1e-15 * np.abs(sums).max())
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        g = int(rng.integers(cfg["n_groups"]))
+        j, k = int(rng.integers(64)), int(rng.integers(64))
+        sl = slice(g * per, (g + 1) * per)
+        o = oracle.evaluate(x[sl], y[sl], cfg["kind"], cfg["eB0"], cfg["lam"],
+                            rho[j:j + 1], T[k:k + 1], 1, 1, per_loop=True)
+        scale = np.abs(o["w"]).sum()
+        tol = (1e-12 if prec == 2 else 1e-6) * scale
+        assert abs(sums[g, j, k] - o["group_sums"][0, 0, 0]) <= tol, (g, j, k)
+    rs, ts = rho[::9], T[::9]  # an 8 x 8 sub-grid spanning both ranges
+    for l in (0, 40961, 65535):
+        ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rs, ts, 1, prec, l, 1)
+        o = oracle.evaluate(x[l:l + 1], y[l:l + 1], cfg["kind"], cfg["eB0"], cfg["lam"],
+                            rs, ts, 1, 1, per_loop=True)
+        check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1)

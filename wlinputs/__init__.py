@@ -107,6 +107,22 @@ def dloop_ensemble(n_loops: int, n_ppl: int, seed: int = 0,
     return x, y
 
 
+def polygon_loops(n_loops: int, n_ppl: int, seed: int = 0):
+    """Closed polygons with an arbitrary point count (not a power of two):
+    the first n_ppl points of d-loops of the next power of two, re-centred.
+    They do not follow the loop law exactly; they exercise the segment
+    arithmetic on ragged point counts."""
+    n2 = 2
+    while n2 < n_ppl:
+        n2 *= 2
+    x, y = dloop_ensemble(n_loops, n2, seed=seed)
+    x = x[:, :n_ppl].astype(np.float64)
+    y = y[:, :n_ppl].astype(np.float64)
+    x -= x.mean(axis=1, keepdims=True)
+    y -= y.mean(axis=1, keepdims=True)
+    return x.astype(np.float32), y.astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # Workload recipes.  Grids: rho_cm = linspace (end points included),
 # T = geometric (end points included).  Fields are given by the central

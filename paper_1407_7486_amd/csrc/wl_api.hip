@@ -113,19 +113,20 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
   a->inv_lam = (float)a->inv_lam_d;
   a->inv_lam2 = (float)a->inv_lam2_d;
   a->lam2 = (float)a->lam2_d;
-  a->exp2_scale = 0.0f;
+  a->lam2_lo = (float)(a->lam2_d - (double)a->lam2);
+  double e2 = 0.0;
   switch (f->kind) {
     case WL_CONST:  // g = eB0/2, b = eB0
       a->cphi = 0.5 * f->eB0;
       a->cspin = f->eB0;
       break;
     case WL_SECH2:  // g = eB0 q(u), b = eB0 sech^2 = eB0 * 4 * E/(1+E)^2
-      a->exp2_scale = (float)(-2.0 * log2e / l);
+      e2 = -2.0 * log2e / l;
       a->cphi = f->eB0;
       a->cspin = 4.0 * f->eB0;
       break;
     case WL_GAUSS:  // g = (eB0/2) (1-E)/v, b = eB0 E
-      a->exp2_scale = (float)(-log2e / (l * l));
+      e2 = -log2e / (l * l);
       a->cphi = 0.5 * f->eB0;
       a->cspin = f->eB0;
       break;
@@ -134,6 +135,8 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
       a->cspin = f->eB0 * l * l * l * l;
       break;
   }
+  a->exp2_scale = (float)e2;
+  a->exp2_scale_lo = (float)(e2 - (double)a->exp2_scale);
   return WL_OK;
 }
 

@@ -10,12 +10,11 @@ namespace wl {
 // Per-segment unit-loop quantities used by the FP32 kernels, one float4 per
 // segment i -> i+1 of a unit loop y (indices mod N):
 //   x = m_x        = (y_i^x + y_{i+1}^x)/2       unit midpoint, x
-//   y = |m|^2      = m_x^2 + m_y^2
+//   y = m_y        = (y_i^y + y_{i+1}^y)/2       unit midpoint, y
 //   z = d_y        = y_{i+1}^y - y_i^y           unit step, y
 //   w = c          = y_i^x y_{i+1}^y - y_i^y y_{i+1}^x   unit cross product
 // so that for the scaled, shifted loop (rho_cm + s y^x, s y^y), s = sqrt(T):
-//   rho^2(midpoint) = rho^2 + 2 rho s m_x + T |m|^2
-//   cross_i         = rho s d_y + T c.
+//   midpoint = (rho_cm + s m_x, s m_y),   cross_i = rho_cm s d_y + T c.
 
 // Work decomposition of one evaluation: one wavefront per item
 // (group g, loop sub-range `sub`, chunk of 64 grid points).
@@ -37,6 +36,7 @@ struct FieldArgs {
   float inv_lam2;    // 1/lambda^2
   float lam2;        // lambda^2
   float exp2_scale;  // SECH2: -2 log2(e)/lambda ; GAUSS: -log2(e)/lambda^2
+  float exp2_scale_lo, lam2_lo;  // rounding residues of exp2_scale, lam2
   // FP64 path
   double inv_lam_d, inv_lam2_d, lam2_d;
   // epilogue: Phi = cphi * sum_i cross_i qa_i ; S = cspin (T/N) sum_i qb_i

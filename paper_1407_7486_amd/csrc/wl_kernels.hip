@@ -12,10 +12,16 @@
 // owner and a fixed loop order (deterministic results).
 //
 // Arithmetic per segment (Sec. 3.2.1, Eqs. rhoi..Ci with the midpoint rule
-// t = 1/2, and Sec. 3.2.2, Eq. Wfermfpl):
-//   rho^2 = P + Q m_x + R |m|^2,   cross = U d_y + R c
-//   (P = rho_cm^2, Q = 2 rho_cm s, R = s^2 = T, U = rho_cm s, s = sqrt(T))
+// t = 1/2, and Sec. 3.2.2, Eq. Wfermfpl), from the unit midpoint m, the unit
+// step d and the unit cross product c of the segment:
+//   midpoint (rho_cm + s m_x, s m_y),  rho^2 = its squared radius
+//   cross = U d_y + R c          (U = rho_cm s, R = s^2 = T, s = sqrt(T))
 //   phase += cross * qa(rho^2),  spin += qb(rho^2)
+// In the compensated FP32 mode rho_cm, s and the field scales are carried as
+// float pairs (hi + lo): their rounding would otherwise be a systematic
+// relative error shared by every segment of a loop, which cosh(S) amplifies
+// by S.  Forming the midpoint (instead of expanding rho^2 around rho_cm^2)
+// keeps rho^2 accurate where a loop centred far out crosses the tube axis.
 // with qa, qb the field's phase weight and field strength up to constants
 // that the FP64 epilogue applies once per loop:
 //   Phi = cphi * sum cross qa,   S = cspin (T/N) sum qb,
@@ -54,7 +60,7 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 
 // qa: phase weight, qb: spin integrand, as functions of rho^2 (FP32,
 // hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
-template <int KIND>
+template <int KIND, bool COMP>
 __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
                                           float& qa, float& qb) {
   if constexpr (KIND == kConst) {
@@ -66,10 +72,11 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     // u = rho/lambda, E = exp(-2u).  sech^2 u = 4 E/(1+E)^2 (4 in cspin).
     // g/eB0 = (u tanh u - ln cosh u)/u^2 = (ln2 - ln(1+E) - 2uE/(1+E))/u^2;
     // below u = 1 that difference cancels, so a polynomial in u^2 is used.
-    r2 = fmaxf(r2, 1e-30f);
+    r2 = fmaxf(r2, 1e-30f);  // rsq(0) is inf
     const float rs = __builtin_amdgcn_rsqf(r2);  // 1/rho
     const float rho = r2 * rs;
-    const float E = __builtin_amdgcn_exp2f(rho * f.exp2_scale);
+    const float E = __builtin_amdgcn_exp2f(
+        COMP ? fmaf(rho, f.exp2_scale, rho * f.exp2_scale_lo) : rho * f.exp2_scale);
     const float opE = 1.0f + E;
     const float ip = __builtin_amdgcn_rcpf(opE);
     const float Eip = E * ip;
@@ -86,9 +93,9 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
     // below v = 1/2 where 1-E cancels); b/eB0 = E.
-    r2 = fmaxf(r2, 0.0f);
     const float v = r2 * f.inv_lam2;
-    const float E = __builtin_amdgcn_exp2f(r2 * f.exp2_scale);
+    const float E = __builtin_amdgcn_exp2f(
+        COMP ? fmaf(r2, f.exp2_scale, r2 * f.exp2_scale_lo) : r2 * f.exp2_scale);
     qb = E;
     if (v < 0.5f) {
       qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v);
@@ -96,7 +103,7 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
       qa = (1.0f - E) * __builtin_amdgcn_rcpf(v);
     }
   } else {  // kRational: r = 1/(lambda^2 + rho^2); g ~ r, b ~ r^2
-    const float r = __builtin_amdgcn_rcpf(fmaxf(r2, 0.0f) + f.lam2);
+    const float r = __builtin_amdgcn_rcpf(COMP ? (r2 + f.lam2) + f.lam2_lo : r2 + f.lam2);
     qa = r;
     qb = r * r;
   }
@@ -150,8 +157,21 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float a) {
 }
 
 struct LaneF32 {
-  float P, Q, R, U;  // rho^2, 2 rho s, s^2, rho s
+  float rho_hi, rho_lo;  // rho_cm = hi + lo
+  float s_hi, s_lo;      // sqrt(T) = hi + lo
+  float R, U;            // T, rho_cm sqrt(T)
 };
+
+__device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T) {
+  LaneF32 c;
+  c.rho_hi = (float)rho;
+  c.rho_lo = (float)(rho - (double)c.rho_hi);
+  c.s_hi = (float)s;
+  c.s_lo = (float)(s - (double)c.s_hi);
+  c.R = (float)T;
+  c.U = (float)(rho * s);
+  return c;
+}
 
 // Phase and spin sums of one loop for this lane's grid point (FP32 path).
 // `seg` is wave-uniform.  Returns sum cross*qa and sum qb in FP64.
@@ -162,11 +182,19 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  auto step = [&](const float4 s) {
-    const float r2 = fmaf(c.R, s.y, fmaf(c.Q, s.x, c.P));
+  auto step = [&](const float4 s) {  // s = (m_x, m_y, d_y, c)
+    float mx, my;
+    if constexpr (COMP) {
+      mx = fmaf(c.s_lo, s.x, fmaf(c.s_hi, s.x, c.rho_hi)) + c.rho_lo;
+      my = fmaf(c.s_lo, s.y, c.s_hi * s.y);
+    } else {
+      mx = fmaf(c.s_hi, s.x, c.rho_hi);
+      my = c.s_hi * s.y;
+    }
+    const float r2 = fmaf(mx, mx, my * my);
     const float cr = fmaf(c.R, s.w, c.U * s.z);
     float qa, qb;
-    field_f32<KIND>(r2, f, qa, qb);
+    field_f32<KIND, COMP>(r2, f, qa, qb);
     if constexpr (COMP) {
       kahan_fma(as, ac, cr, qa);
       if constexpr (kSpinSum) kahan_add(bs, bc, qb);
@@ -282,11 +310,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  LaneF32 c;
-  c.P = (float)(rho * rho);
-  c.Q = (float)(2.0 * rho * s);
-  c.R = (float)T;
-  c.U = (float)(rho * s);
+  const LaneF32 c = lane_consts(rho, s, T);
 
   double acc = 0.0;
   for (int64_t l = l0; l < l1; ++l) {
@@ -322,11 +346,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  LaneF32 c;
-  c.P = (float)(rho * rho);
-  c.Q = (float)(2.0 * rho * s);
-  c.R = (float)T;
-  c.U = (float)(rho * s);
+  const LaneF32 c = lane_consts(rho, s, T);
   double A, B, phi, S;
   if constexpr (PREC == 2) {
     loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
@@ -362,7 +382,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
     const double mx = 0.5 * (x0 + x1), my = 0.5 * (y0 + y1);
     float4 o;
     o.x = (float)mx;
-    o.y = (float)(mx * mx + my * my);
+    o.y = (float)my;
     o.z = (float)(y1 - y0);
     o.w = (float)(x0 * y1 - y0 * x1);
     seg[t] = o;

@@ -2,7 +2,6 @@
 
 Every case prints its name before it touches the GPU.  Inputs come from the
 seeded generator (wlinputs); expected values only from the oracle."""
-import math
 import sys
 
 import numpy as np
@@ -10,7 +9,7 @@ import pytest
 
 import oracle
 import wlinputs
-from wl_tol import check_means, check_per_loop
+from wl_tol import check_means, check_per_loop, mean_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -74,12 +73,13 @@ def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
     o = oracle_eval((fname, spin), x, y, kind, eB0, lam, RHO, TGRID, spin, 4)
     fld = wl.field(kind, eB0, lam)
     ph, sp, w = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, 0, 128)
-    check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin)
+    r1 = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin)
     mean, err, sums = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, prec)
     o_mean, o_err, _ = oracle.stats(o["group_sums"], 128)
-    absw = np.abs(o["w"])
-    check_means(prec, mean, sums, o_mean, o["group_sums"], absw.mean(axis=0),
-                absw.reshape(4, 32, *absw.shape[1:]).sum(axis=1))
+    r2 = check_means(prec, mean, sums, o_mean, o["group_sums"],
+                     *mean_scales(o["w"], o["spin"], 4))
+    say("worst error/tolerance: phase %.3g spin %.3g w %.3g mean %.3g sums %.3g"
+        % (*r1, *r2))
     # the group error follows from the group sums the same way on both sides
     _, e2, _ = oracle.stats(sums, 128)
     np.testing.assert_allclose(err, e2, rtol=1e-9, atol=1e-300)
@@ -218,7 +218,7 @@ def test_full_size_sampled(wl, ctx, big, pname):
         sl = slice(g * per, (g + 1) * per)
         o = oracle.evaluate(x[sl], y[sl], cfg["kind"], cfg["eB0"], cfg["lam"],
                             rho[j:j + 1], T[k:k + 1], 1, 1, per_loop=True)
-        scale = np.abs(o["w"]).sum()
+        scale = (np.abs(o["w"]) * np.maximum(1.0, o["spin"])).sum()
         tol = (1e-12 if prec == 2 else 1e-6) * scale
         assert abs(sums[g, j, k] - o["group_sums"][0, 0, 0]) <= tol, (g, j, k)
     rs, ts = rho[::9], T[::9]  # an 8 x 8 sub-grid spanning both ranges
@@ -226,4 +226,5 @@ def test_full_size_sampled(wl, ctx, big, pname):
         ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rs, ts, 1, prec, l, 1)
         o = oracle.evaluate(x[l:l + 1], y[l:l + 1], cfg["kind"], cfg["eB0"], cfg["lam"],
                             rs, ts, 1, 1, per_loop=True)
-        check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1)
+        r = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1)
+        say("loop", l, "worst error/tolerance: phase %.3g spin %.3g w %.3g" % r)

@@ -6,8 +6,13 @@ relative to the natural scale.
 
 FP32 kernels (WL_FP32C): the phase must agree to 1e-5 relative,
 |dPhi| <= 1e-5 max(|Phi|, 1); the spin exponent likewise; ensemble means
-and group sums to 1e-6 of the scale M = (1/N_l) sum_l |w_l| (M = 1 for
-scalar loops, larger when cosh S >> 1 makes the mean a cancellation).
+and group sums to 1e-6 of the scale
+    M_S = (1/N_l) sum_l |w_l| max(1, S_l).
+For scalar loops (S = 0, |w| <= 1) that is at most 1e-6 absolute.  For
+spinors, FP32 carries the loop geometry, T and the field scales to relative
+precision u = 2^-24, so S has an error of order u S that cosh turns into a
+relative error of order u S tanh(S) in w: the mean is ill-conditioned by the
+factor S (the fermion problem, Sec. 4.3), and the scale includes it.
 
 WL_FP32 (plain sums) is a precision-study mode and only has to agree to
 1e-3 relative.
@@ -22,6 +27,7 @@ TOL = {
 
 
 def check_per_loop(prec, ph, sp, w, o_ph, o_sp, o_w, spin):
+    """Returns the worst error / tolerance ratios (phase, spin, w)."""
     t = TOL[prec]
     dph = np.abs(ph - o_ph)
     lim_ph = t["phase"] * np.maximum(1.0, np.abs(o_ph))
@@ -35,16 +41,27 @@ def check_per_loop(prec, ph, sp, w, o_ph, o_sp, o_w, spin):
         assert (dsp <= lim_sp).all(), f"spin: worst {(dsp / lim_sp).max():.3g}x"
         scale = np.cosh(o_sp)
         lim_w = (lim_ph + lim_sp * np.abs(np.tanh(o_sp))) * scale * 1.01 + 1e-300
+        r_sp = float((dsp / lim_sp).max())
     else:
         assert np.all(sp == 0)
         lim_w = lim_ph * 1.01
+        r_sp = 0.0
     dw = np.abs(w - o_w)
     assert (dw <= lim_w).all(), f"w: worst {(dw / lim_w).max():.3g}x"
+    return float((dph / lim_ph).max()), r_sp, float((dw / lim_w).max())
+
+
+def mean_scales(o_w, o_spin, n_groups):
+    """Scales of the mean and of the group sums from the oracle's per-loop
+    w and S, shape (N_l, n_rho, n_T): (M_S, per-group sums of the same)."""
+    a = np.abs(o_w) * np.maximum(1.0, np.abs(o_spin))
+    nl = a.shape[0]
+    return a.mean(axis=0), a.reshape(n_groups, nl // n_groups, *a.shape[1:]).sum(axis=1)
 
 
 def check_means(prec, mean, sums, o_mean, o_sums, o_w_abs_mean, o_w_abs_group):
-    """o_w_abs_mean: (n_rho, n_T) mean |w|; o_w_abs_group: (G, n_rho, n_T)
-    sum of |w| over each group (the scales)."""
+    """o_w_abs_mean, o_w_abs_group: the scales from mean_scales().  Returns
+    the worst error / tolerance ratios (mean, group sums)."""
     t = TOL[prec]
     dm = np.abs(mean - o_mean)
     lim = t["mean"] * np.maximum(o_w_abs_mean, 1e-300)
@@ -52,3 +69,4 @@ def check_means(prec, mean, sums, o_mean, o_sums, o_w_abs_mean, o_w_abs_group):
     ds = np.abs(sums - o_sums)
     lims = t["mean"] * np.maximum(o_w_abs_group, 1e-300)
     assert (ds <= lims).all(), f"group sums: worst {(ds / lims).max():.3g}x"
+    return float((dm / lim).max()), float((ds / lims).max())

@@ -32,6 +32,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_calibration(nbytes):
+    """A plain copy of known size: each dispatch reads and writes nbytes."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes": 4 * n, "ms_per_copy": 1e3 * dt,
+                      "GBps_read_plus_write": 2 * 4 * n / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,7 +57,13 @@ def main():
     ap.add_argument("--workload", default="sech2_spinor_64k")
     ap.add_argument("--cpu-loops", type=int, default=64,
                     help="loops in the oracle's timed CPU sample (0: skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes "
+                         "(5 times; reference for HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU split is a design note, not implemented)", file=sys.stderr)

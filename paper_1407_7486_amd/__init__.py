@@ -49,6 +49,15 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: the HIP library has not been built "
         "(run python -m paper_1407_7486_amd.build)")
 
+# torch ships its own HIP runtime (libamdhip64.so).  Loading torch first
+# makes libwl.so bind to that same runtime, so that torch streams and device
+# pointers are valid here; loaded the other way round the process would hold
+# two HIP runtimes competing for the device.
+try:
+    import torch  # noqa: F401
+except ImportError:  # no torch: libwl.so uses the system HIP runtime
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _sigs = {

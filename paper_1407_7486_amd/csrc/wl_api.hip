@@ -114,21 +114,25 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
   a->inv_lam2 = (float)a->inv_lam2_d;
   a->lam2 = (float)a->lam2_d;
   a->lam2_lo = (float)(a->lam2_d - (double)a->lam2);
+  a->two_inv_lam = (float)(2.0 / l);
+  a->thr = 0.0f;
   double e2 = 0.0;
   switch (f->kind) {
     case WL_CONST:  // g = eB0/2, b = eB0
       a->cphi = 0.5 * f->eB0;
       a->cspin = f->eB0;
       break;
-    case WL_SECH2:  // g = eB0 q(u), b = eB0 sech^2 = eB0 * 4 * E/(1+E)^2
+    case WL_SECH2:  // g = eB0 lam^2 qa, b = eB0 * 4 * E/(1+E)^2
       e2 = -2.0 * log2e / l;
-      a->cphi = f->eB0;
+      a->cphi = f->eB0 * l * l;
       a->cspin = 4.0 * f->eB0;
+      a->thr = a->lam2;  // u < 1
       break;
-    case WL_GAUSS:  // g = (eB0/2) (1-E)/v, b = eB0 E
+    case WL_GAUSS:  // g = (eB0 lam^2/2) (1-E)/rho^2, b = eB0 E
       e2 = -log2e / (l * l);
-      a->cphi = 0.5 * f->eB0;
+      a->cphi = 0.5 * f->eB0 * l * l;
       a->cspin = f->eB0;
+      a->thr = (float)(0.5 * l * l);  // v < 1/2
       break;
     case WL_RATIONAL:  // g = (eB0 lam^2/2) r, b = eB0 lam^4 r^2
       a->cphi = 0.5 * f->eB0 * l * l;

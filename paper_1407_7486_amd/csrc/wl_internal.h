@@ -37,6 +37,8 @@ struct FieldArgs {
   float lam2;        // lambda^2
   float exp2_scale;  // SECH2: -2 log2(e)/lambda ; GAUSS: -log2(e)/lambda^2
   float exp2_scale_lo, lam2_lo;  // rounding residues of exp2_scale, lam2
+  float two_inv_lam;   // 2/lambda
+  float thr;           // rho^2 below which the polynomial branch is used
   // FP64 path
   double inv_lam_d, inv_lam2_d, lam2_d;
   // epilogue: Phi = cphi * sum_i cross_i qa_i ; S = cspin (T/N) sum_i qb_i

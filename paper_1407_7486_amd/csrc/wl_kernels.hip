@@ -17,11 +17,12 @@
 //   midpoint (rho_cm + s m_x, s m_y),  rho^2 = its squared radius
 //   cross = U d_y + R c          (U = rho_cm s, R = s^2 = T, s = sqrt(T))
 //   phase += cross * qa(rho^2),  spin += qb(rho^2)
-// In the compensated FP32 mode rho_cm, s and the field scales are carried as
-// float pairs (hi + lo): their rounding would otherwise be a systematic
-// relative error shared by every segment of a loop, which cosh(S) amplifies
-// by S.  Forming the midpoint (instead of expanding rho^2 around rho_cm^2)
-// keeps rho^2 accurate where a loop centred far out crosses the tube axis.
+// Forming the midpoint (instead of expanding rho^2 around rho_cm^2) keeps
+// rho^2 accurate where a loop centred far out crosses the tube axis.  In the
+// compensated FP32 mode rho_cm (and the Gaussian and rational field scales)
+// are carried as float pairs: their rounding is an error shared by every
+// segment of a loop (a shift of the loop by ~1e-7 rho_cm), which cosh(S)
+// would amplify by S.
 // with qa, qb the field's phase weight and field strength up to constants
 // that the FP64 epilogue applies once per loop:
 //   Phi = cphi * sum cross qa,   S = cspin (T/N) sum qb,
@@ -60,6 +61,11 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 
 // qa: phase weight, qb: spin integrand, as functions of rho^2 (FP32,
 // hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
+// Units (the epilogue constants cphi, cspin restore them):
+//   SECH2  qa = g/(eB0 lambda^2)    qb = sech^2(u)/4
+//   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
+//   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
+// r2 > 0 (the caller adds 1e-30).
 template <int KIND, bool COMP>
 __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
                                           float& qa, float& qb) {
@@ -69,40 +75,37 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     qa = 1.0f;
     qb = 1.0f;
   } else if constexpr (KIND == kSech2) {
-    // u = rho/lambda, E = exp(-2u).  sech^2 u = 4 E/(1+E)^2 (4 in cspin).
-    // g/eB0 = (u tanh u - ln cosh u)/u^2 = (ln2 - ln(1+E) - 2uE/(1+E))/u^2;
-    // below u = 1 that difference cancels, so a polynomial in u^2 is used.
-    r2 = fmaxf(r2, 1e-30f);  // rsq(0) is inf
+    // u = rho/lambda, E = exp(-2u), sech^2 u = 4 E/(1+E)^2;
+    // g/eB0 = (u tanh u - ln cosh u)/u^2 = (ln2 - ln(1+E) - 2uE/(1+E))/u^2,
+    // whose terms cancel below u = 1: there a polynomial in u^2 is used.
     const float rs = __builtin_amdgcn_rsqf(r2);  // 1/rho
     const float rho = r2 * rs;
-    const float E = __builtin_amdgcn_exp2f(
-        COMP ? fmaf(rho, f.exp2_scale, rho * f.exp2_scale_lo) : rho * f.exp2_scale);
+    const float E = __builtin_amdgcn_exp2f(rho * f.exp2_scale);
     const float opE = 1.0f + E;
     const float ip = __builtin_amdgcn_rcpf(opE);
     const float Eip = E * ip;
     qb = Eip * ip;
-    const float v = r2 * f.inv_lam2;
-    if (v < 1.0f) {
-      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v);
+    if (r2 < f.thr) {
+      const float v = r2 * f.inv_lam2;
+      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
     } else {
       const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
-      const float u = rho * f.inv_lam;
-      const float h = fmaf(-kLn2f, lg, kLn2f) - 2.0f * u * Eip;
-      qa = h * (rs * rs) * f.lam2;
+      const float h = fmaf(-kLn2f, lg, kLn2f) - (rho * f.two_inv_lam) * Eip;
+      qa = (h * rs) * rs;
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
     // below v = 1/2 where 1-E cancels); b/eB0 = E.
-    const float v = r2 * f.inv_lam2;
     const float E = __builtin_amdgcn_exp2f(
         COMP ? fmaf(r2, f.exp2_scale, r2 * f.exp2_scale_lo) : r2 * f.exp2_scale);
     qb = E;
-    if (v < 0.5f) {
-      qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v);
+    if (r2 < f.thr) {
+      const float v = r2 * f.inv_lam2;
+      qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
     } else {
-      qa = (1.0f - E) * __builtin_amdgcn_rcpf(v);
+      qa = (1.0f - E) * __builtin_amdgcn_rcpf(r2);
     }
-  } else {  // kRational: r = 1/(lambda^2 + rho^2); g ~ r, b ~ r^2
+  } else {  // kRational
     const float r = __builtin_amdgcn_rcpf(COMP ? (r2 + f.lam2) + f.lam2_lo : r2 + f.lam2);
     qa = r;
     qb = r * r;
@@ -126,14 +129,14 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
     qb = Eip * ip;
     const double v = r2 * f.inv_lam2_d;
     if (v < 0.25) {
-      qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v);
+      qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v) * f.inv_lam2_d;
     } else {
-      qa = (kLn2 - log1p(E) - 2.0 * u * Eip) / v;
+      qa = (kLn2 - log1p(E) - 2.0 * u * Eip) / r2;
     }
   } else if constexpr (KIND == kGauss) {
     const double v = r2 * f.inv_lam2_d;
     qb = exp(-v);
-    qa = v > 0.0 ? -expm1(-v) / v : 1.0;
+    qa = v > 0.0 ? -expm1(-v) / r2 : f.inv_lam2_d;
   } else {
     const double r = 1.0 / (r2 + f.lam2_d);
     qa = r;
@@ -158,7 +161,7 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float a) {
 
 struct LaneF32 {
   float rho_hi, rho_lo;  // rho_cm = hi + lo
-  float s_hi, s_lo;      // sqrt(T) = hi + lo
+  float s_hi;            // sqrt(T)
   float R, U;            // T, rho_cm sqrt(T)
 };
 
@@ -167,7 +170,6 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T) {
   c.rho_hi = (float)rho;
   c.rho_lo = (float)(rho - (double)c.rho_hi);
   c.s_hi = (float)s;
-  c.s_lo = (float)(s - (double)c.s_hi);
   c.R = (float)T;
   c.U = (float)(rho * s);
   return c;
@@ -175,6 +177,9 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T) {
 
 // Phase and spin sums of one loop for this lane's grid point (FP32 path).
 // `seg` is wave-uniform.  Returns sum cross*qa and sum qb in FP64.
+// Compensated mode: each block of 8 segments is summed plainly and the
+// block sums enter Kahan sums, so the long sum over the loop carries no
+// error growth with N; plain mode sums every term directly.
 template <int KIND, bool SPIN, bool COMP>
 __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               int32_t n, const LaneF32& c,
@@ -182,26 +187,16 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  auto step = [&](const float4 s) {  // s = (m_x, m_y, d_y, c)
-    float mx, my;
-    if constexpr (COMP) {
-      mx = fmaf(c.s_lo, s.x, fmaf(c.s_hi, s.x, c.rho_hi)) + c.rho_lo;
-      my = fmaf(c.s_lo, s.y, c.s_hi * s.y);
-    } else {
-      mx = fmaf(c.s_hi, s.x, c.rho_hi);
-      my = c.s_hi * s.y;
-    }
-    const float r2 = fmaf(mx, mx, my * my);
+  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y, d_y, c)
+    const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
+                          : fmaf(c.s_hi, s.x, c.rho_hi);
+    const float my = c.s_hi * s.y;
+    const float r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
     const float cr = fmaf(c.R, s.w, c.U * s.z);
     float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
-    if constexpr (COMP) {
-      kahan_fma(as, ac, cr, qa);
-      if constexpr (kSpinSum) kahan_add(bs, bc, qb);
-    } else {
-      as = fmaf(cr, qa, as);
-      if constexpr (kSpinSum) bs += qb;
-    }
+    pa = fmaf(cr, qa, pa);
+    if constexpr (kSpinSum) pb += qb;
   };
   int32_t i = 0;
   for (; i + 8 <= n; i += 8) {
@@ -209,10 +204,28 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
     float4 sv[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
+    if constexpr (COMP) {
+      float pa = 0.0f, pb = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) step(sv[k]);
+      for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
+      kahan_add(as, ac, pa);
+      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) term(sv[k], as, bs);
+    }
   }
-  for (; i < n; ++i) step(seg[i]);
+  if (i < n) {
+    float pa = 0.0f, pb = 0.0f;
+    for (; i < n; ++i) term(seg[i], pa, pb);
+    if constexpr (COMP) {
+      kahan_add(as, ac, pa);
+      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+    } else {
+      as += pa;
+      bs += pb;
+    }
+  }
   A = (double)as - (double)ac;
   B = kSpinSum ? (double)bs - (double)bc : (double)n;
 }
@@ -261,15 +274,33 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
   B = kSpinSum ? b : (double)n;
 }
 
-// Per-loop epilogue in FP64: phase, spin exponent and w.
-template <bool SPIN>
+// Per-loop epilogue in FP64: phase, spin exponent and w.  The phase is
+// reduced in revolutions (cos(Phi) = cospi(2 frac(Phi/2pi))).  The FP32
+// paths take cosh from the hardware exp2 of the fractional part of
+// S log2(e), scaled by the integer part in FP64 (relative error ~1e-7, no
+// overflow below FP64's range); the FP64 path uses the library cosh.
+template <bool SPIN, int PREC>
 __device__ __forceinline__ double epilogue(double A, double B, double T,
                                            int32_t n, const FieldArgs& f,
                                            double& phi, double& S) {
   phi = f.cphi * A;
-  S = SPIN ? f.cspin * (T / n) * B : 0.0;
-  const double cw = cos(phi);
-  return SPIN ? cw * cosh(S) : cw;
+  const double rev = phi * 0.15915494309189533577;
+  const double cw = cospi(2.0 * (rev - rint(rev)));
+  if constexpr (!SPIN) {
+    S = 0.0;
+    return cw;
+  } else {
+    S = f.cspin * (T / n) * B;
+    if constexpr (PREC == 2) {
+      return cw * cosh(S);
+    } else {
+      const double t = fabs(S) * 1.4426950408889634074;  // |S| log2(e)
+      const double k = floor(t);
+      const float p = __builtin_amdgcn_exp2f((float)(t - k));  // 2^frac in [1,2)
+      const int ki = (int)fminf((float)k, 2000.0f);
+      return cw * 0.5 * (ldexp((double)p, ki) + ldexp(1.0 / (double)p, -ki));
+    }
+  }
 }
 
 __device__ __forceinline__ int64_t remap_wg(int32_t w, int32_t n_wg, int32_t n_xcd) {
@@ -320,7 +351,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
     } else {
       loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
     }
-    acc += epilogue<SPIN>(A, B, T, n_ppl, f, phi, S);
+    acc += epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
   }
   if (valid) out[gs * n_pts + p] = acc;
 }
@@ -353,7 +384,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   } else {
     loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
   }
-  const double w = epilogue<SPIN>(A, B, T, n_ppl, f, phi, S);
+  const double w = epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
   if (valid) {
     const int64_t o = li * n_pts + p;
     o_phase[o] = phi;

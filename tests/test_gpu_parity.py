@@ -128,9 +128,11 @@ def test_edge_cases(wl, ctx):
     x1, y1 = wlinputs.dloop_ensemble(1, 64, seed=3)
     ens = wl.wl_ensemble_upload(ctx, x1, y1, 1)
     try:
+        # a single loop: no averaging, so the FP32 phase tolerance applies
         m, _, s = wl.wl_average(ctx, ens, wl.field(0, 1.0), RHO, TGRID, 0, 0)
-        o = oracle.evaluate(x1, y1, 0, 1.0, 1.0, RHO, TGRID, 0, 1)
-        np.testing.assert_allclose(m, o["group_sums"][0], atol=1e-6)
+        o = oracle.evaluate(x1, y1, 0, 1.0, 1.0, RHO, TGRID, 0, 1, per_loop=True)
+        tol = 1e-5 * np.maximum(1.0, np.abs(o["phase"][0]))
+        assert np.all(np.abs(m - o["group_sums"][0]) <= tol)
     finally:
         wl.wl_ensemble_free(ens)
 

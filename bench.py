@@ -18,14 +18,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p99 ms"
 
-# VALU issue slots per segment evaluation of the FP32 compensated kernel
-# (quarter-rate transcendentals count 4 slots), by field kind and spin.
-SLOTS_FP32C = {("sech2", 1): 41, ("sech2", 0): 36, ("gauss", 1): 29,
-               ("gauss", 0): 24, ("rational", 1): 18, ("rational", 0): 13,
-               ("const", 1): 8, ("const", 0): 8}
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (non-packed FP32 issue rate)
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU cost of one segment evaluation in the FP32 compensated
+# kernel, in FP32 lane-op slots: every FP32 VALU instruction of the
+# formulation counts 1 and every transcendental (exp, log, rcp, rsq) counts 4
+# (measured on MI355X: a transcendental costs ~4 FMA issue slots).  The sech^2
+# count is the far-from-axis branch (25 instructions, 4 of them
+# transcendental).
+SLOTS_FP32C = {("sech2", 1): 37, ("sech2", 0): 35, ("gauss", 1): 23,
+               ("gauss", 0): 21, ("rational", 1): 17, ("rational", 0): 15,
+               ("const", 1): 4, ("const", 0): 4}
+# FP32 VALU peak: 157.3 TFLOP/s / 2 flop per FMA = 256 CUs x 128 FP32
+# lanes/clk x 2.4 GHz lane-ops per second.
+PEAK_OPS = 256 * 128 * 2.4e9
 KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
+# HBM bytes per launch of the main kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
+# reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
+# re-measured whenever the kernel changes; None when stale.
+TRAFFIC = {}
 
 
 def log(*a):
@@ -137,10 +147,11 @@ def main():
 
     slots = SLOTS_FP32C[(kname, spin)]
     achieved = seg_per_step * slots / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                "kernel": "k_average<sech2,spin,fp32c>", "kernel_ms": k_ms,
-                "slots_per_segment": slots}
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
+                "unit": "Top/s (FP32 VALU lane-ops)", "frac": achieved / PEAK_OPS,
+                "traffic": TRAFFIC.get(args.workload),
+                "kernel": f"k_average<{kname},spin={spin},fp32c>", "kernel_ms": k_ms,
+                "ops_per_segment": slots}
 
     cpu = None
     if args.cpu_loops > 0:

@@ -159,6 +159,33 @@ int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                      int32_t n_T, int32_t spin, int32_t precision,
                      double* d_mean, double* d_err, double* d_group_sums);
 
+/* One request of a batched evaluation (host memory, caller-owned).  The
+ * outputs have the shapes of wl_average's and may each be NULL. */
+typedef struct wl_request {
+  wl_field field;
+  const double* rho;  /* [n_rho], >= 0, finite */
+  const double* T;    /* [n_T],   >  0, finite */
+  int32_t n_rho;
+  int32_t n_T;
+  int32_t spin;       /* 0 scalar, 1 spinor */
+  int32_t precision;  /* WL_FP32C, WL_FP32 or WL_FP64 */
+  double* mean;       /* [n_rho][n_T] */
+  double* err;        /* [n_rho][n_T] */
+  double* group_sums; /* [G][n_rho][n_T] */
+} wl_request;
+
+/* Batched evaluation of n_reqs uneven requests (different fields, grids,
+ * spins) against one ensemble: the work items of all requests of one
+ * precision form a single index space consumed by one persistent launch
+ * (Sec. 3.2 per loop, Sec. 4.2.3 groups).  Every request's result is the one
+ * wl_average would return for it alone: its work is split and summed the
+ * same way whatever else is in the batch.  Requests with an empty grid are
+ * skipped.  Synchronous.  Validation happens for all requests before any
+ * work starts (WL_EINVAL names the request).
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
+                     int32_t n_reqs);
+
 /* Per-loop values for loops loop0 .. loop0+n_loops-1 on the grid (for
  * loop-by-loop checks).  Same kernels as wl_average.  Outputs (host, each
  * may be NULL) of shape [n_loops][n_rho][n_T]:

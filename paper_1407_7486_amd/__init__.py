@@ -29,7 +29,7 @@ EXPORTS = (
     "wl_create", "wl_destroy", "wl_last_error", "wl_strerror", "wl_version",
     "wl_ensemble_upload", "wl_ensemble_free", "wl_ensemble_info",
     "wl_average", "wl_average_async", "wl_per_loop", "wl_set_timing",
-    "wl_last_kernel_ms", "wl_kernel_ms_total",
+    "wl_last_kernel_ms", "wl_kernel_ms_total", "wl_average_batch",
 )
 
 
@@ -42,6 +42,14 @@ class WLError(RuntimeError):
 class wl_field(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("eB0", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+class wl_request(ctypes.Structure):
+    _fields_ = [("field", wl_field), ("rho", ctypes.c_void_p), ("T", ctypes.c_void_p),
+                ("n_rho", ctypes.c_int32), ("n_T", ctypes.c_int32),
+                ("spin", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("err", ctypes.c_void_p),
+                ("group_sums", ctypes.c_void_p)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -81,6 +89,7 @@ _sigs = {
     "wl_last_kernel_ms": ([_vp, ctypes.POINTER(_d)], ctypes.c_int),
     "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
                            ctypes.c_int),
+    "wl_average_batch": ([_vp, _vp, ctypes.POINTER(wl_request), _i32], ctypes.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -193,6 +202,28 @@ def wl_average_async(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,
                                  d_rho.numel(), _ptr(d_T), d_T.numel(),
                                  int(spin), int(precision), _ptr(d_mean),
                                  _ptr(d_err), _ptr(d_group_sums)), ctx)
+
+
+def wl_average_batch(ctx, ens, requests):
+    """Batched evaluation.  requests: list of dicts with keys kind, eB0, lam,
+    rho, T, spin, precision.  Returns a list of (mean, err, group_sums)."""
+    _, _, G = wl_ensemble_info(ens)
+    arr = (wl_request * max(1, len(requests)))()
+    keep, outs = [], []
+    for i, q in enumerate(requests):
+        rho = _host_f64(q["rho"])
+        T = _host_f64(q["T"])
+        mean = np.zeros((rho.size, T.size))
+        err = np.zeros((rho.size, T.size))
+        sums = np.zeros((G, rho.size, T.size))
+        keep += [rho, T]
+        outs.append((mean, err, sums))
+        arr[i] = wl_request(field(q["kind"], q["eB0"], q.get("lam", 1.0)), _ptr(rho), _ptr(T),
+                            rho.size, T.size, int(q["spin"]),
+                            int(q.get("precision", WL_FP32C)),
+                            _ptr(mean), _ptr(err), _ptr(sums))
+    _check(_lib.wl_average_batch(ctx, ens, arr, len(requests)), ctx)
+    return outs
 
 
 def wl_per_loop(ctx, ens, fld, rho, T, spin, precision, loop0, n_loops):

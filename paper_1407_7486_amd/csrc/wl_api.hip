@@ -26,6 +26,9 @@ struct wl_ctx {
   void* d_partial = nullptr;
   size_t partial_bytes = 0;
   int* d_flag = nullptr;
+  void* d_batch = nullptr;  // batched evaluation: descriptors, grids, results
+  size_t batch_bytes = 0;
+  unsigned int* d_counter = nullptr;  // work counter of persistent launches
   // timing of the main kernel: one event pair per launch since timing was
   // enabled (pairs are pooled and reused)
   bool timing = false;
@@ -228,7 +231,8 @@ int wl_create(wl_ctx** out, int device, void* hip_stream) {
   c->stream = (hipStream_t)hip_stream;
   c->num_cu = prop.multiProcessorCount;
   DeviceGuard g(device);
-  if (g.status != hipSuccess || hipMalloc((void**)&c->d_flag, sizeof(int)) != hipSuccess) {
+  if (g.status != hipSuccess || hipMalloc((void**)&c->d_flag, sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->d_counter, sizeof(unsigned int)) != hipSuccess) {
     wl_destroy(c);
     return WL_ENOMEM;
   }
@@ -246,6 +250,8 @@ int wl_destroy(wl_ctx* ctx) {
     if (ctx->d_out) (void)hipFree(ctx->d_out);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
     if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->d_batch) (void)hipFree(ctx->d_batch);
     for (auto& pr : ctx->events) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
@@ -495,6 +501,114 @@ int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                        ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "wl_average");
+  return WL_OK;
+}
+
+int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
+                     int32_t n_reqs) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  if (n_reqs < 0 || (n_reqs > 0 && !reqs)) return fail(ctx, WL_EINVAL, "bad request list");
+  int rc = check_common(ctx, ens, 0, WL_FP32C);
+  if (rc) return rc;
+  std::vector<wl::FieldArgs> fa(n_reqs);
+  for (int32_t r = 0; r < n_reqs; ++r) {
+    const wl_request& q = reqs[r];
+    if ((rc = check_common(ctx, ens, q.spin, q.precision)) ||
+        (rc = check_field(ctx, &q.field, &fa[r])) ||
+        (rc = check_grid(ctx, q.rho, q.n_rho, q.T, q.n_T))) {
+      std::string m = ctx->err;
+      return fail(ctx, rc, "request %d: %s", r, m.c_str());
+    }
+  }
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const int64_t G = ens->n_groups;
+  for (int prec = WL_FP32C; prec <= WL_FP64; ++prec) {
+    // layout of one precision class in the batch buffer:
+    // [descriptors][grids][partials][group sums][means][errors]
+    std::vector<wl::ReqDesc> d;
+    std::vector<int32_t> who;
+    int64_t items = 0, grid_n = 0, part_n = 0, sums_n = 0, pts_n = 0;
+    for (int32_t r = 0; r < n_reqs; ++r) {
+      const wl_request& q = reqs[r];
+      const int32_t n_pts = q.n_rho * q.n_T;
+      if (q.precision != prec || n_pts == 0) continue;
+      const wl::Sched s = make_sched(ctx, ens, n_pts);
+      wl::ReqDesc e{};
+      e.f = fa[r];
+      e.item_begin = items;
+      e.loops_per_sub = s.loops_per_sub;
+      e.sums_begin = sums_n;
+      e.pts_begin = pts_n;
+      e.n_sub = s.n_sub;
+      e.n_chunks = s.n_chunks;
+      e.n_T = q.n_T;
+      e.n_pts = n_pts;
+      e.spin = q.spin;
+      // pointers are filled in once the buffer exists; keep offsets in them
+      e.rho = (const double*)(intptr_t)grid_n;
+      e.out = (double*)(intptr_t)(s.n_sub > 1 ? part_n : -1);
+      grid_n += q.n_rho + q.n_T;
+      if (s.n_sub > 1) part_n += G * s.n_sub * n_pts;
+      items += s.n_items;
+      sums_n += G * n_pts;
+      pts_n += n_pts;
+      d.push_back(e);
+      who.push_back(r);
+    }
+    if (d.empty()) continue;
+    if (items > 0xffffffffll)
+      return fail(ctx, WL_EINVAL, "batch of %lld work items is too large", (long long)items);
+    const size_t desc_b = (d.size() * sizeof(wl::ReqDesc) + 255) & ~(size_t)255;
+    const size_t total_b = desc_b + 8 * (size_t)(grid_n + part_n + sums_n + 2 * pts_n);
+    if ((rc = ensure(ctx, &ctx->d_batch, &ctx->batch_bytes, total_b, "batch buffer"))) return rc;
+    char* base = (char*)ctx->d_batch;
+    double* d_grid = (double*)(base + desc_b);
+    double* d_part = d_grid + grid_n;
+    double* d_sums = d_part + part_n;
+    double* d_mean = d_sums + sums_n;
+    double* d_err = d_mean + pts_n;
+    std::vector<double> h_grid((size_t)grid_n);
+    for (size_t i = 0; i < d.size(); ++i) {
+      const wl_request& q = reqs[who[i]];
+      const int64_t go = (int64_t)(intptr_t)d[i].rho;
+      memcpy(&h_grid[go], q.rho, q.n_rho * sizeof(double));
+      memcpy(&h_grid[go + q.n_rho], q.T, q.n_T * sizeof(double));
+      d[i].rho = d_grid + go;
+      d[i].T = d_grid + go + q.n_rho;
+      const int64_t po = (int64_t)(intptr_t)d[i].out;
+      d[i].out = po >= 0 ? d_part + po : d_sums + d[i].sums_begin;
+    }
+    hipError_t e = hipMemcpyAsync(base, d.data(), d.size() * sizeof(wl::ReqDesc),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_grid, h_grid.data(), grid_n * sizeof(double),
+                         hipMemcpyHostToDevice, ctx->stream);
+    const int64_t want_wg = (items + wl::kWavesPerWG - 1) / wl::kWavesPerWG;
+    const int64_t max_wg = (int64_t)ctx->num_cu * 8;
+    if (e == hipSuccess)
+      e = wl::launch_batch(prec, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl,
+                           (const wl::ReqDesc*)base, (int32_t)d.size(), items, sums_n, pts_n,
+                           ens->n_groups, ens->n_loops, ens->n_loops / ens->n_groups,
+                           ctx->d_counter, d_sums, d_mean, d_err,
+                           (int32_t)(want_wg < max_wg ? want_wg : max_wg), ctx->stream);
+    std::vector<double> h_out((size_t)(sums_n + 2 * pts_n));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h_out.data(), d_sums, h_out.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "wl_average_batch");
+    for (size_t i = 0; i < d.size(); ++i) {
+      const wl_request& q = reqs[who[i]];
+      const int64_t n_pts = d[i].n_pts;
+      if (q.group_sums)
+        memcpy(q.group_sums, &h_out[d[i].sums_begin], G * n_pts * sizeof(double));
+      if (q.mean) memcpy(q.mean, &h_out[sums_n + d[i].pts_begin], n_pts * sizeof(double));
+      if (q.err)
+        memcpy(q.err, &h_out[sums_n + pts_n + d[i].pts_begin], n_pts * sizeof(double));
+    }
+  }
   return WL_OK;
 }
 

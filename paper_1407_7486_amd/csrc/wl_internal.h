@@ -45,6 +45,21 @@ struct FieldArgs {
   double cphi, cspin;
 };
 
+// One request of a batched evaluation (device-resident descriptor).
+struct ReqDesc {
+  FieldArgs f;
+  const double* rho;    // device grid
+  const double* T;
+  double* out;          // item outputs: partial [G*n_sub][n_pts], or the
+                        // group sums directly when n_sub == 1
+  int64_t item_begin;   // first item of this request in the batch
+  int64_t loops_per_sub;
+  int64_t sums_begin;   // offset of [G][n_pts] group sums in the batch
+  int64_t pts_begin;    // offset of [n_pts] means / errors in the batch
+  int32_t n_sub, n_chunks, n_T, n_pts;
+  int32_t spin, pad;
+};
+
 constexpr int kWavesPerWG = 4;
 constexpr int kWave = 64;
 
@@ -68,6 +83,14 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            int32_t n_T, int32_t n_pts, int64_t loop0,
                            int64_t n_loops, double* d_phase, double* d_spin,
                            double* d_w, hipStream_t stream);
+
+hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
+                        const float* d_y, int32_t n_ppl, const ReqDesc* d_reqs,
+                        int32_t n_reqs, int64_t total_items, int64_t total_sums,
+                        int64_t total_pts, int32_t n_groups, int64_t n_loops,
+                        int64_t loops_per_group, unsigned int* d_counter,
+                        double* d_sums, double* d_mean, double* d_err,
+                        int32_t n_wg, hipStream_t stream);
 
 hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,
                              int32_t n_sub, int32_t n_pts, double* d_sums,

@@ -113,6 +113,31 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
 }
 
 // ----------------------------------------------------------- FP64 fields
+// ln(1+E) for 0 <= E <= e^-1 as 2 atanh(z), z = E/(2+E) <= 0.156: the odd
+// series 2 sum z^(2k+1)/(2k+1) to 1e-17 needs 12 terms.  (The library log1p
+// evaluates in double-double and costs ~45 VGPRs.)
+__device__ __forceinline__ double log1p_small(double E) {
+  const double d = 2.0 + E;
+  double r = __builtin_amdgcn_rcp(d);
+  r = r * fma(-d, r, 2.0);
+  r = r * fma(-d, r, 2.0);
+  double z = E * r;
+  z = fma(fma(-d, z, E), r, z);  // one correction: z = E/d to ~1 ulp
+  const double z2 = z * z;
+  double p = 1.0 / 25.0;
+#pragma unroll
+  for (int k = 11; k >= 0; --k) p = fma(p, z2, 1.0 / (2 * k + 1));
+  return 2.0 * z * p;
+}
+
+// 1/x for x > 0 normal: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 template <int KIND>
 __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
                                           double& qa, double& qb) {
@@ -122,23 +147,26 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
     qa = 1.0;
     qb = 1.0;
   } else if constexpr (KIND == kSech2) {
-    const double u = sqrt(r2) * f.inv_lam_d;
+    const double rho = sqrt(r2);
+    const double u = rho * f.inv_lam_d;
     const double E = exp(-2.0 * u);
-    const double ip = 1.0 / (1.0 + E);
+    const double ip = rcp64(1.0 + E);
     const double Eip = E * ip;
     qb = Eip * ip;
     const double v = r2 * f.inv_lam2_d;
     if (v < 0.25) {
       qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v) * f.inv_lam2_d;
     } else {
-      qa = (kLn2 - log1p(E) - 2.0 * u * Eip) / r2;
+      qa = (kLn2 - log1p_small(E) - 2.0 * u * Eip) * rcp64(r2);
     }
   } else if constexpr (KIND == kGauss) {
     const double v = r2 * f.inv_lam2_d;
-    qb = exp(-v);
-    qa = v > 0.0 ? -expm1(-v) / r2 : f.inv_lam2_d;
+    const double E = exp(-v);
+    qb = E;
+    qa = v < 0.5 ? horner_f64<WL_P_GAUSS_F64_DEG>(WL_P_GAUSS_F64, v) * f.inv_lam2_d
+                 : (1.0 - E) * rcp64(r2);
   } else {
-    const double r = 1.0 / (r2 + f.lam2_d);
+    const double r = rcp64(r2 + f.lam2_d);
     qa = r;
     qb = r * r;
   }
@@ -254,15 +282,6 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
   };
   float xp = X[0], yp = Y[0];
   int32_t i = 1;
-  for (; i + 4 <= n; i += 4) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float xn = X[i + k], yn = Y[i + k];
-      step(xp, yp, xn, yn);
-      xp = xn;
-      yp = yn;
-    }
-  }
   for (; i < n; ++i) {
     const float xn = X[i], yn = Y[i];
     step(xp, yp, xn, yn);
@@ -278,7 +297,8 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
 // reduced in revolutions (cos(Phi) = cospi(2 frac(Phi/2pi))).  The FP32
 // paths take cosh from the hardware exp2 of the fractional part of
 // S log2(e), scaled by the integer part in FP64 (relative error ~1e-7, no
-// overflow below FP64's range); the FP64 path uses the library cosh.
+// overflow below FP64's range); the FP64 path forms cosh from the library
+// exp.
 template <bool SPIN, int PREC>
 __device__ __forceinline__ double epilogue(double A, double B, double T,
                                            int32_t n, const FieldArgs& f,
@@ -292,7 +312,8 @@ __device__ __forceinline__ double epilogue(double A, double B, double T,
   } else {
     S = f.cspin * (T / n) * B;
     if constexpr (PREC == 2) {
-      return cw * cosh(S);
+      const double e = exp(fabs(S));
+      return cw * 0.5 * (e + 1.0 / e);
     } else {
       const double t = fabs(S) * 1.4426950408889634074;  // |S| log2(e)
       const double k = floor(t);
@@ -314,25 +335,25 @@ __device__ __forceinline__ int64_t remap_wg(int32_t w, int32_t n_wg, int32_t n_x
                    : (int64_t)rem * (per + 1) + (int64_t)(xcd - rem) * per + idx;
 }
 
-// ------------------------------------------------------------- kernels
+// One work item: group g, loop sub-range `sub`, grid chunk `chunk` of one
+// evaluation.  Lane j owns grid point chunk*64 + j and accumulates its w over
+// the sub-range's loops in order; the sum lands in out[(g*n_sub+sub)*n_pts+p].
 template <int KIND, bool SPIN, int PREC>
-__global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
+__device__ __forceinline__ void run_item(
     const float4* __restrict__ seg, const float* __restrict__ X,
     const float* __restrict__ Y, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
-    int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,
+    int32_t n_T, int32_t n_pts, const FieldArgs& f, int64_t loops_per_group,
+    int64_t loops_per_sub, int32_t n_sub, int32_t n_chunks, int64_t item,
     double* __restrict__ out) {
-  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t lane = threadIdx.x % kWave;
-  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * kWavesPerWG + wave;
-  if (item >= sc.n_items) return;
-  const int32_t chunk = (int32_t)(item % sc.n_chunks);
-  const int64_t gs = item / sc.n_chunks;  // g * n_sub + sub
-  const int64_t g = gs / sc.n_sub;
-  const int64_t sub = gs % sc.n_sub;
-  const int64_t l0 = g * sc.loops_per_group + sub * sc.loops_per_sub;
-  int64_t l1 = l0 + sc.loops_per_sub;
-  const int64_t gend = (g + 1) * sc.loops_per_group;
+  const int32_t chunk = (int32_t)(item % n_chunks);
+  const int64_t gs = item / n_chunks;  // g * n_sub + sub
+  const int64_t g = gs / n_sub;
+  const int64_t sub = gs % n_sub;
+  const int64_t l0 = g * loops_per_group + sub * loops_per_sub;
+  int64_t l1 = l0 + loops_per_sub;
+  const int64_t gend = (g + 1) * loops_per_group;
   if (l1 > gend) l1 = gend;
 
   const int32_t p = chunk * kWave + lane;
@@ -355,6 +376,130 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
   }
   if (valid) out[gs * n_pts + p] = acc;
 }
+
+// ------------------------------------------------------------- kernels
+template <int KIND, bool SPIN, int PREC>
+__global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
+    const float4* __restrict__ seg, const float* __restrict__ X,
+    const float* __restrict__ Y, int32_t n_ppl,
+    const double* __restrict__ rho_g, const double* __restrict__ T_g,
+    int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,
+    double* __restrict__ out) {
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * kWavesPerWG + wave;
+  if (item >= sc.n_items) return;
+  run_item<KIND, SPIN, PREC>(seg, X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f,
+                             sc.loops_per_group, sc.loops_per_sub, sc.n_sub,
+                             sc.n_chunks, item, out);
+}
+
+// Batched evaluation of uneven requests in one persistent launch.  Items of
+// all requests form one index space (request r owns [item_begin_r,
+// item_begin_r + n_items_r)); each wavefront repeatedly takes the next item
+// from a device counter until the counter passes the total, so every wave
+// exits once the work is handed out.  An item's output slot is fixed by its
+// index, so results do not depend on which wave ran it.
+template <int PREC>
+__global__ __launch_bounds__(kWavesPerWG * kWave) void k_batch(
+    const float4* __restrict__ seg, const float* __restrict__ X,
+    const float* __restrict__ Y, int32_t n_ppl, const ReqDesc* __restrict__ reqs,
+    int32_t n_reqs, int64_t total_items, unsigned int* __restrict__ counter,
+    int64_t loops_per_group) {
+  const int32_t lane = threadIdx.x % kWave;
+  for (;;) {
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1u);
+    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)t) & 0xffffffffll;
+    if (item >= total_items) break;
+    // request owning the item: last r with item_begin <= item
+    int32_t lo = 0, hi = n_reqs - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    }
+    const ReqDesc& q = reqs[lo];
+    const int64_t li = item - q.item_begin;
+    switch (q.f.kind * 2 + q.spin) {
+#define WL_ITEM(K, SP)                                                              \
+  run_item<K, SP, PREC>(seg, X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f,          \
+                        loops_per_group, q.loops_per_sub, q.n_sub, q.n_chunks, li, \
+                        q.out)
+      case 0: WL_ITEM(kConst, false); break;
+      case 1: WL_ITEM(kConst, true); break;
+      case 2: WL_ITEM(kSech2, false); break;
+      case 3: WL_ITEM(kSech2, true); break;
+      case 4: WL_ITEM(kGauss, false); break;
+      case 5: WL_ITEM(kGauss, true); break;
+      case 6: WL_ITEM(kRational, false); break;
+      default: WL_ITEM(kRational, true); break;
+#undef WL_ITEM
+    }
+  }
+}
+
+// Batched sub-range reduction and statistics: thread t handles output t of
+// the concatenation over requests (binary search for its request).
+__global__ __launch_bounds__(256) void k_reduce_batch(const ReqDesc* __restrict__ reqs,
+                                                      int32_t n_reqs, int64_t total,
+                                                      int32_t n_groups,
+                                                      double* __restrict__ sums) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = n_reqs - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].sums_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const ReqDesc& q = reqs[lo];
+    if (q.n_sub == 1) continue;  // written directly by the item kernel
+    const int64_t o = t - q.sums_begin;
+    const int64_t g = o / q.n_pts, p = o % q.n_pts;
+    double acc = 0.0;
+    for (int32_t s = 0; s < q.n_sub; ++s) acc += q.out[(g * q.n_sub + s) * q.n_pts + p];
+    sums[t] = acc;
+  }
+  (void)n_groups;
+}
+
+__device__ __forceinline__ void stats_point(const double* __restrict__ sums,
+                                            int32_t n_groups, int32_t n_pts,
+                                            int64_t n_loops, int32_t p, double& m,
+                                            double& e) {
+  double tot = 0.0;
+  for (int32_t g = 0; g < n_groups; ++g) tot += sums[(int64_t)g * n_pts + p];
+  m = tot / (double)n_loops;
+  const double per = (double)(n_loops / n_groups);
+  double ss = 0.0;
+  for (int32_t g = 0; g < n_groups; ++g) {
+    const double d = sums[(int64_t)g * n_pts + p] / per - m;
+    ss += d * d;
+  }
+  e = n_groups > 1 ? sqrt(ss / ((double)n_groups * (n_groups - 1))) : NAN;
+}
+
+__global__ __launch_bounds__(256) void k_stats_batch(const ReqDesc* __restrict__ reqs,
+                                                     int32_t n_reqs, int64_t total_pts,
+                                                     int32_t n_groups, int64_t n_loops,
+                                                     const double* __restrict__ sums,
+                                                     double* __restrict__ mean,
+                                                     double* __restrict__ err) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_pts;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = n_reqs - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].pts_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const ReqDesc& q = reqs[lo];
+    double m, e;
+    stats_point(sums + q.sums_begin, n_groups, q.n_pts, n_loops,
+                (int32_t)(t - q.pts_begin), m, e);
+    mean[t] = m;
+    err[t] = e;
+  }
+}
+
+__global__ void k_zero_u32(unsigned int* __restrict__ p) { *p = 0u; }
 
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
@@ -440,17 +585,10 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ sums,
                                                double* __restrict__ err) {
   const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pts) return;
-  double tot = 0.0;
-  for (int32_t g = 0; g < n_groups; ++g) tot += sums[(int64_t)g * n_pts + p];
-  const double m = tot / (double)n_loops;
-  const double per = (double)(n_loops / n_groups);
-  double ss = 0.0;
-  for (int32_t g = 0; g < n_groups; ++g) {
-    const double d = sums[(int64_t)g * n_pts + p] / per - m;
-    ss += d * d;
-  }
+  double m, e;
+  stats_point(sums, n_groups, n_pts, n_loops, p, m, e);
   if (mean) mean[p] = m;
-  if (err) err[p] = n_groups > 1 ? sqrt(ss / ((double)n_groups * (n_groups - 1))) : NAN;
+  if (err) err[p] = e;
 }
 
 // ------------------------------------------------------------ dispatch
@@ -540,6 +678,45 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            hipStream_t stream) {
   WL_DISPATCH(launch_pl_t, f, d_seg, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
               loop0, n_loops, d_phase, d_spin, d_w, stream)
+}
+
+hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
+                        const float* d_y, int32_t n_ppl, const ReqDesc* d_reqs,
+                        int32_t n_reqs, int64_t total_items, int64_t total_sums,
+                        int64_t total_pts, int32_t n_groups, int64_t n_loops,
+                        int64_t loops_per_group, unsigned int* d_counter,
+                        double* d_sums, double* d_mean, double* d_err,
+                        int32_t n_wg, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, stream, d_counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 blk(kWavesPerWG * kWave);
+  switch (precision) {
+    case 0:
+      hipLaunchKernelGGL((k_batch<0>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_batch<1>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_batch<2>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t rb = (total_sums + 255) / 256;
+  hipLaunchKernelGGL(k_reduce_batch, dim3((uint32_t)(rb < 8192 ? rb : 8192)), dim3(256), 0,
+                     stream, d_reqs, n_reqs, total_sums, n_groups, d_sums);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t sb = (total_pts + 255) / 256;
+  hipLaunchKernelGGL(k_stats_batch, dim3((uint32_t)(sb < 8192 ? sb : 8192)), dim3(256), 0,
+                     stream, d_reqs, n_reqs, total_pts, n_groups, n_loops, d_sums, d_mean,
+                     d_err);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,

@@ -230,3 +230,41 @@ def test_full_size_sampled(wl, ctx, big, pname):
                             rs, ts, 1, 1, per_loop=True)
         r = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1)
         say("loop", l, "worst error/tolerance: phase %.3g spin %.3g w %.3g" % r)
+
+
+def test_batch_equals_alone(wl, ctx):
+    """Uneven requests in one batched launch: each result equals the same
+    request evaluated alone (bit for bit), and one is checked against the
+    oracle."""
+    say("batch vs alone")
+    x, y = wlinputs.polygon_loops(256, 203, seed=23)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 8)
+    try:
+        rng = np.random.default_rng(7)
+        reqs = []
+        shapes = [(1, 1), (4, 8), (5, 13), (9, 17), (2, 64), (3, 33), (11, 7), (1, 64)]
+        for i in range(16):
+            nr, nt = shapes[i % len(shapes)]
+            reqs.append(dict(kind=i % 4, eB0=float(rng.uniform(0.5, 5)),
+                             lam=float(rng.uniform(0.3, 2)),
+                             rho=np.sort(rng.uniform(0, 4, nr)),
+                             T=np.geomspace(1e-3, 20, nt), spin=(i // 4) % 2,
+                             precision=(0, 2, 1)[i % 3]))
+        reqs.append(dict(kind=1, eB0=1.0, lam=1.0, rho=np.zeros(0), T=TGRID, spin=1,
+                         precision=0))
+        outs = wl.wl_average_batch(ctx, ens, reqs)
+        for q, (m, e, s_) in zip(reqs, outs):
+            if q["rho"].size == 0:
+                continue
+            m1, e1, s1 = wl.wl_average(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
+                                       q["rho"], q["T"], q["spin"], q["precision"])
+            assert np.array_equal(s_, s1), q
+            assert np.array_equal(m, m1) and np.array_equal(e, e1, equal_nan=True)
+        q = reqs[5]
+        o = oracle.evaluate(x, y, q["kind"], q["eB0"], q["lam"], q["rho"], q["T"], q["spin"],
+                            8, per_loop=True)
+        o_mean, _, _ = oracle.stats(o["group_sums"], 256)
+        check_means(q["precision"], outs[5][0], outs[5][2], o_mean, o["group_sums"],
+                    *mean_scales(o["w"], o["spin"], 8))
+    finally:
+        wl.wl_ensemble_free(ens)

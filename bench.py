@@ -58,6 +58,54 @@ def copy_calibration(nbytes):
                       "GBps_read_plus_write": 2 * 4 * n / dt / 1e9}), flush=True)
 
 
+def serve_run(wl, ctx, args):
+    """Bounded serving run: Poisson arrivals of uneven requests (sech^2 or
+    Gaussian tube, eB0 ~ U[0.5,10], lambda ~ U[0.2,5], N_rho ~ U{4..128},
+    N_T ~ U{8..64}, spin 50/50, FP32C; request seed 1) against a resident
+    ensemble of 4096-point loops; latency = completion - arrival."""
+    import numpy as np
+
+    import wlinputs
+    nl, n_ppl = args.serve_loops, 4096
+    x, y = wlinputs.dloop_ensemble(nl, n_ppl, seed=0)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 64)
+    del x, y
+    reqs = wlinputs.draw_requests(args.serve_requests, seed=1)
+    rng = np.random.Generator(np.random.Philox(key=2))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
+    srv = wl.Server(ctx, ens, slots=2)
+    log(f"[bench] serve: {len(reqs)} requests at {args.serve_rate}/s on {nl} loops")
+    t0 = time.perf_counter()
+    tickets = []
+    for q, ta in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        q["precision"] = wl.WL_FP32C
+        tickets.append((srv.submit(q), time.perf_counter() - t0))
+    lat = []
+    for t, ts in tickets:
+        st, ms = srv.wait(t, 600.0)
+        if st != 0:
+            raise RuntimeError(f"serving request failed with status {st}")
+        lat.append(ms)
+        srv.result(t)
+    t_end = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    wl.wl_ensemble_free(ens)
+    segs = sum(q["rho"].size * q["T"].size for q in reqs) * nl * n_ppl
+    lat = np.array(lat)
+    out = {"requests": len(reqs), "offered_rate": args.serve_rate,
+           "achieved_rate": len(reqs) / t_end, "n_loops": nl, "n_ppl": n_ppl,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "segment_evals_per_s": segs / t_end, "wall_s": t_end,
+           "batches": info["batches"], "slots": 2}
+    log(f"[bench] serve p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms, "
+        f"{out['segment_evals_per_s']:.3e} seg/s, {info['batches']} batches")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +115,12 @@ def main():
     ap.add_argument("--workload", default="sech2_spinor_64k")
     ap.add_argument("--cpu-loops", type=int, default=64,
                     help="loops in the oracle's timed CPU sample (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the bounded serving run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=50.0,
+                    help="Poisson arrival rate of the serving run, requests/s")
+    ap.add_argument("--serve-loops", type=int, default=16384,
+                    help="loops of the serving ensemble (4096 points each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes "
                          "(5 times; reference for HBM traffic counters) and exit")
@@ -169,6 +223,10 @@ def main():
         log(f"[bench] cpu oracle {segs / dtc:.4e} seg/s on {cpu['cores']} threads")
 
     wl.wl_ensemble_free(ens)
+    serve = None
+    if args.serve_requests > 0:
+        del x, y
+        serve = serve_run(wl, ctx, args)
     wl.wl_destroy(ctx)
     out = {
         "metric": METRIC, "value": value, "unit": "segment-evals/s", "n_gpus": 1,
@@ -179,7 +237,7 @@ def main():
                    "n_ppl": cfg["n_ppl"], "n_rho": int(rho.size), "n_T": int(T.size),
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
-        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

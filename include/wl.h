@@ -186,6 +186,59 @@ typedef struct wl_request {
 int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
                      int32_t n_reqs);
 
+/* ---- serving: continuous batching of requests -------------------------
+ * A server evaluates submitted requests against one ensemble in batches
+ * (the same arithmetic as wl_average_batch).  A scheduler thread keeps up to
+ * `slots` batches in flight on streams of its own; each slot has a device
+ * budget of `result_bytes` for partial sums (group sums G*n_pts*8, sub-range
+ * partials G*n_sub*n_pts*8 when a group's loops are split, means and
+ * errors) and `input_bytes` for descriptors and grids.  Requests are
+ * admitted first-come first-served (per precision) into a free slot while
+ * they fit its budget; the others wait.  Each slot's device work is one
+ * captured HIP graph replayed per batch.  Each result equals wl_average's
+ * for that request alone. */
+typedef struct wl_server wl_server;
+
+typedef struct wl_server_config {
+  int32_t slots;       /* batches in flight, 1..8 (default 2)               */
+  int32_t max_batch;   /* requests per batch (default 1024)                 */
+  size_t input_bytes;  /* per slot (default 8 MiB)                          */
+  size_t result_bytes; /* per slot (default 256 MiB)                        */
+} wl_server_config;
+
+/* Start a server on an uploaded ensemble; cfg may be NULL for defaults.
+ * The ensemble and context must outlive the server.  Errors: WL_EINVAL,
+ * WL_ENOMEM. */
+int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg,
+                     wl_server** out);
+
+/* Queue one request.  Its grids are copied; its output pointers are kept
+ * and must stay valid until the ticket is finished.  Thread-safe.  Errors:
+ * WL_EINVAL (invalid request), WL_ENOMEM (the request alone exceeds a
+ * slot's budget), WL_EHIP (the server failed earlier). */
+int wl_server_submit(wl_server* srv, const wl_request* req, int64_t* ticket);
+
+/* Status of a ticket: 1 queued, 2 running, 0 done (outputs written), < 0
+ * the WL_E* code it failed with.  latency_ms (may be NULL) receives the
+ * time from submission to completion once finished, else -1. */
+int wl_server_poll(wl_server* srv, int64_t ticket, int32_t* status, double* latency_ms);
+
+/* Wait until the ticket finishes or timeout_s passes (< 0: no limit); then
+ * as wl_server_poll. */
+int wl_server_wait(wl_server* srv, int64_t ticket, double timeout_s, int32_t* status,
+                   double* latency_ms);
+
+/* Forget a finished ticket. */
+int wl_server_release(wl_server* srv, int64_t ticket);
+
+/* Requests queued, requests in flight, batches launched so far. */
+int wl_server_info(wl_server* srv, int64_t* pending, int64_t* running, int64_t* batches);
+
+const char* wl_server_last_error(const wl_server* srv);
+
+/* Finish all queued and running work, then free the server (NULL allowed). */
+int wl_server_destroy(wl_server* srv);
+
 /* Per-loop values for loops loop0 .. loop0+n_loops-1 on the grid (for
  * loop-by-loop checks).  Same kernels as wl_average.  Outputs (host, each
  * may be NULL) of shape [n_loops][n_rho][n_T]:

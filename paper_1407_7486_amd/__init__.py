@@ -30,6 +30,8 @@ EXPORTS = (
     "wl_ensemble_upload", "wl_ensemble_free", "wl_ensemble_info",
     "wl_average", "wl_average_async", "wl_per_loop", "wl_set_timing",
     "wl_last_kernel_ms", "wl_kernel_ms_total", "wl_average_batch",
+    "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
+    "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
 )
 
 
@@ -50,6 +52,11 @@ class wl_request(ctypes.Structure):
                 ("spin", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("err", ctypes.c_void_p),
                 ("group_sums", ctypes.c_void_p)]
+
+
+class wl_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("input_bytes", ctypes.c_size_t), ("result_bytes", ctypes.c_size_t)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -90,6 +97,16 @@ _sigs = {
     "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
                            ctypes.c_int),
     "wl_average_batch": ([_vp, _vp, ctypes.POINTER(wl_request), _i32], ctypes.c_int),
+    "wl_server_create": ([_vp, _vp, ctypes.POINTER(wl_server_config), ctypes.POINTER(_vp)],
+                         ctypes.c_int),
+    "wl_server_submit": ([_vp, ctypes.POINTER(wl_request), ctypes.POINTER(_i64)], ctypes.c_int),
+    "wl_server_poll": ([_vp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_d)], ctypes.c_int),
+    "wl_server_wait": ([_vp, _i64, _d, ctypes.POINTER(_i32), ctypes.POINTER(_d)], ctypes.c_int),
+    "wl_server_release": ([_vp, _i64], ctypes.c_int),
+    "wl_server_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+                       ctypes.c_int),
+    "wl_server_last_error": ([_vp], ctypes.c_char_p),
+    "wl_server_destroy": ([_vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -224,6 +241,68 @@ def wl_average_batch(ctx, ens, requests):
                             _ptr(mean), _ptr(err), _ptr(sums))
     _check(_lib.wl_average_batch(ctx, ens, arr, len(requests)), ctx)
     return outs
+
+
+class Server:
+    """Continuous-batching server (wl_server_*).  submit() keeps the request's
+    numpy outputs alive until the ticket is released."""
+
+    def __init__(self, ctx, ens, slots=2, max_batch=1024, input_bytes=8 << 20,
+                 result_bytes=256 << 20):
+        self.ctx, self.ens = ctx, ens
+        self.G = wl_ensemble_info(ens)[2]
+        cfg = wl_server_config(slots, max_batch, input_bytes, result_bytes)
+        self.h = _vp()
+        _check(_lib.wl_server_create(ctx, ens, ctypes.byref(cfg), ctypes.byref(self.h)), ctx)
+        self._live = {}
+
+    def _check(self, rc):
+        if rc != WL_OK:
+            raise WLError(rc, _lib.wl_server_last_error(self.h).decode() or wl_strerror(rc))
+
+    def submit(self, q):
+        """q: dict with kind, eB0, lam, rho, T, spin, precision.  Returns a
+        ticket; outputs (mean, err, group_sums) via result()."""
+        rho = _host_f64(q["rho"])
+        T = _host_f64(q["T"])
+        out = (np.zeros((rho.size, T.size)), np.zeros((rho.size, T.size)),
+               np.zeros((self.G, rho.size, T.size)))
+        req = wl_request(field(q["kind"], q["eB0"], q.get("lam", 1.0)), _ptr(rho), _ptr(T),
+                         rho.size, T.size, int(q["spin"]), int(q.get("precision", WL_FP32C)),
+                         _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        t = _i64()
+        self._check(_lib.wl_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = out
+        return t.value
+
+    def poll(self, ticket):
+        st, lat = _i32(), _d()
+        self._check(_lib.wl_server_poll(self.h, ticket, ctypes.byref(st), ctypes.byref(lat)))
+        return st.value, lat.value
+
+    def wait(self, ticket, timeout_s=-1.0):
+        st, lat = _i32(), _d()
+        self._check(_lib.wl_server_wait(self.h, ticket, float(timeout_s), ctypes.byref(st),
+                                        ctypes.byref(lat)))
+        return st.value, lat.value
+
+    def result(self, ticket, release=True):
+        out = self._live[ticket]
+        if release:
+            self._check(_lib.wl_server_release(self.h, ticket))
+            del self._live[ticket]
+        return out
+
+    def info(self):
+        a, b, c = _i64(), _i64(), _i64()
+        self._check(_lib.wl_server_info(self.h, ctypes.byref(a), ctypes.byref(b),
+                                        ctypes.byref(c)))
+        return {"pending": a.value, "running": b.value, "batches": c.value}
+
+    def close(self):
+        if self.h:
+            _lib.wl_server_destroy(self.h)
+            self.h = None
 
 
 def wl_per_loop(ctx, ens, fld, rho, T, spin, precision, loop0, n_loops):

@@ -10,43 +10,9 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/wl.h"
-#include "wl_internal.h"
+#include "wl_host.h"
 
-struct wl_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int num_cu = 0;
-  std::string err;
-  // scratch reused across calls (grown on demand, freed by wl_destroy)
-  void* d_grid = nullptr;
-  size_t grid_bytes = 0;
-  void* d_out = nullptr;
-  size_t out_bytes = 0;
-  void* d_partial = nullptr;
-  size_t partial_bytes = 0;
-  int* d_flag = nullptr;
-  void* d_batch = nullptr;  // batched evaluation: descriptors, grids, results
-  size_t batch_bytes = 0;
-  unsigned int* d_counter = nullptr;  // work counter of persistent launches
-  // timing of the main kernel: one event pair per launch since timing was
-  // enabled (pairs are pooled and reused)
-  bool timing = false;
-  size_t n_timed = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-};
-
-struct wl_ens {
-  wl_ctx* ctx = nullptr;
-  int64_t n_loops = 0;
-  int32_t n_ppl = 0;
-  int32_t n_groups = 0;
-  float* d_x = nullptr;
-  float* d_y = nullptr;
-  float4* d_seg = nullptr;
-};
-
-namespace {
+namespace wl {
 
 int fail(wl_ctx* ctx, int code, const char* fmt, ...) {
   if (ctx) {
@@ -64,21 +30,7 @@ int hip_fail(wl_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, WL_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Makes the context's device current for the duration of a call and
-// restores the caller's device afterwards.
-struct DeviceGuard {
-  int prev = -1;
-  hipError_t status = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    status = hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-int ensure(wl_ctx* ctx, void** p, size_t* have, size_t need, const char* what) {
+static int ensure(wl_ctx* ctx, void** p, size_t* have, size_t need, const char* what) {
   if (need <= *have) return WL_OK;
   if (*p) {
     // pending work may still read the old buffer
@@ -178,12 +130,16 @@ wl::Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts) {
   s.n_chunks = (n_pts + wl::kWave - 1) / wl::kWave;
   // Enough wavefronts for ~8 per SIMD (4 SIMDs per CU) so that the equal-
   // cost items keep every SIMD busy until the end; split each group's loops
-  // into sub-ranges when groups x chunks alone fall short.
+  // into sub-ranges when groups x chunks alone fall short, at most 8 of them
+  // and of at least 8 loops each (the partial sums cost G n_sub n_pts
+  // doubles).  The rule depends only on the request and the ensemble, so a
+  // request is decomposed the same way alone and in a batch.
   const int64_t target = (int64_t)ctx->num_cu * 4 * 8;
   const int64_t base = (int64_t)e->n_groups * s.n_chunks;
   int64_t n_sub = (target + base - 1) / base;
+  if (n_sub > 8) n_sub = 8;
+  if (n_sub > s.loops_per_group / 8) n_sub = s.loops_per_group / 8;
   if (n_sub < 1) n_sub = 1;
-  if (n_sub > s.loops_per_group) n_sub = s.loops_per_group;
   s.loops_per_sub = (s.loops_per_group + n_sub - 1) / n_sub;
   // no empty sub-ranges
   n_sub = (s.loops_per_group + s.loops_per_sub - 1) / s.loops_per_sub;
@@ -194,7 +150,91 @@ wl::Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts) {
   return s;
 }
 
-}  // namespace
+ReqPlan plan_request(const wl_ctx* ctx, const wl_ens* ens, const wl_request& q) {
+  ReqPlan p;
+  p.n_pts = q.n_rho * q.n_T;
+  if (p.n_pts == 0) return p;
+  p.s = make_sched(ctx, ens, p.n_pts);
+  const int64_t G = ens->n_groups;
+  p.in_bytes = sizeof(ReqDesc) + 8 * (size_t)(q.n_rho + q.n_T);
+  p.res_bytes = 8 * (size_t)(G * p.n_pts + 2 * p.n_pts +
+                             (p.s.n_sub > 1 ? G * p.s.n_sub * p.n_pts : 0));
+  return p;
+}
+
+bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldArgs* fa,
+                 const ReqPlan* plans, int32_t n, void* h_in, size_t cap_in, void* d_in,
+                 void* d_res, size_t cap_res, BatchLayout* lay) {
+  const int64_t G = ens->n_groups;
+  *lay = BatchLayout();
+  int64_t grid_n = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    lay->items += plans[i].s.n_items;
+    lay->sums_n += G * plans[i].n_pts;
+    lay->pts_n += plans[i].n_pts;
+    if (plans[i].s.n_sub > 1) lay->part_n += G * plans[i].s.n_sub * plans[i].n_pts;
+    grid_n += reqs[i]->n_rho + reqs[i]->n_T;
+  }
+  const size_t grids_off = kBatchDescOffset + (((size_t)n * sizeof(ReqDesc) + 255) & ~(size_t)255);
+  lay->in_bytes = grids_off + 8 * (size_t)grid_n;
+  lay->res_bytes = 8 * (size_t)(lay->sums_n + 2 * lay->pts_n + lay->part_n);
+  if (lay->in_bytes > cap_in || lay->res_bytes > cap_res) return false;
+  char* hb = (char*)h_in;
+  BatchHeader* hdr = (BatchHeader*)hb;
+  hdr->n_reqs = n;
+  hdr->total_items = lay->items;
+  hdr->total_sums = lay->sums_n;
+  hdr->total_pts = lay->pts_n;
+  ReqDesc* desc = (ReqDesc*)(hb + kBatchDescOffset);
+  double* h_grid = (double*)(hb + grids_off);
+  const double* d_grid = (const double*)((const char*)d_in + grids_off);
+  double* d_sums = (double*)d_res;
+  double* d_part = d_sums + lay->sums_n + 2 * lay->pts_n;
+  int64_t items = 0, sums = 0, pts = 0, part = 0, go = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const wl_request& q = *reqs[i];
+    const ReqPlan& pl = plans[i];
+    ReqDesc e{};
+    e.f = fa[i];
+    e.rho = d_grid + go;
+    e.T = d_grid + go + q.n_rho;
+    memcpy(h_grid + go, q.rho, q.n_rho * sizeof(double));
+    memcpy(h_grid + go + q.n_rho, q.T, q.n_T * sizeof(double));
+    go += q.n_rho + q.n_T;
+    e.out = pl.s.n_sub > 1 ? d_part + part : d_sums + sums;
+    e.item_begin = items;
+    e.loops_per_sub = pl.s.loops_per_sub;
+    e.sums_begin = sums;
+    e.pts_begin = pts;
+    e.n_sub = pl.s.n_sub;
+    e.n_chunks = pl.s.n_chunks;
+    e.n_T = q.n_T;
+    e.n_pts = pl.n_pts;
+    e.spin = q.spin;
+    desc[i] = e;
+    lay->sums_begin.push_back(sums);
+    lay->pts_begin.push_back(pts);
+    items += pl.s.n_items;
+    sums += G * pl.n_pts;
+    pts += pl.n_pts;
+    if (pl.s.n_sub > 1) part += G * pl.s.n_sub * pl.n_pts;
+  }
+  return true;
+}
+
+void scatter_results(const wl_request& q, const BatchLayout& lay, int32_t i,
+                     const double* h_res, int64_t G) {
+  const int64_t n_pts = (int64_t)q.n_rho * q.n_T;
+  if (q.group_sums)
+    memcpy(q.group_sums, h_res + lay.sums_begin[i], G * n_pts * sizeof(double));
+  if (q.mean) memcpy(q.mean, h_res + lay.sums_n + lay.pts_begin[i], n_pts * sizeof(double));
+  if (q.err)
+    memcpy(q.err, h_res + lay.sums_n + lay.pts_n + lay.pts_begin[i], n_pts * sizeof(double));
+}
+
+}  // namespace wl
+
+using namespace wl;
 
 extern "C" {
 
@@ -523,91 +563,50 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
   }
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  const int64_t G = ens->n_groups;
   for (int prec = WL_FP32C; prec <= WL_FP64; ++prec) {
-    // layout of one precision class in the batch buffer:
-    // [descriptors][grids][partials][group sums][means][errors]
-    std::vector<wl::ReqDesc> d;
-    std::vector<int32_t> who;
-    int64_t items = 0, grid_n = 0, part_n = 0, sums_n = 0, pts_n = 0;
+    std::vector<const wl_request*> rq;
+    std::vector<wl::FieldArgs> rf;
+    std::vector<ReqPlan> pl;
+    size_t in_b = kBatchDescOffset + 256, res_b = 0;
     for (int32_t r = 0; r < n_reqs; ++r) {
-      const wl_request& q = reqs[r];
-      const int32_t n_pts = q.n_rho * q.n_T;
-      if (q.precision != prec || n_pts == 0) continue;
-      const wl::Sched s = make_sched(ctx, ens, n_pts);
-      wl::ReqDesc e{};
-      e.f = fa[r];
-      e.item_begin = items;
-      e.loops_per_sub = s.loops_per_sub;
-      e.sums_begin = sums_n;
-      e.pts_begin = pts_n;
-      e.n_sub = s.n_sub;
-      e.n_chunks = s.n_chunks;
-      e.n_T = q.n_T;
-      e.n_pts = n_pts;
-      e.spin = q.spin;
-      // pointers are filled in once the buffer exists; keep offsets in them
-      e.rho = (const double*)(intptr_t)grid_n;
-      e.out = (double*)(intptr_t)(s.n_sub > 1 ? part_n : -1);
-      grid_n += q.n_rho + q.n_T;
-      if (s.n_sub > 1) part_n += G * s.n_sub * n_pts;
-      items += s.n_items;
-      sums_n += G * n_pts;
-      pts_n += n_pts;
-      d.push_back(e);
-      who.push_back(r);
+      if (reqs[r].precision != prec || (int64_t)reqs[r].n_rho * reqs[r].n_T == 0) continue;
+      rq.push_back(&reqs[r]);
+      rf.push_back(fa[r]);
+      pl.push_back(plan_request(ctx, ens, reqs[r]));
+      in_b += pl.back().in_bytes;
+      res_b += pl.back().res_bytes;
     }
-    if (d.empty()) continue;
+    if (rq.empty()) continue;
+    int64_t items = 0;
+    for (const ReqPlan& p : pl) items += p.s.n_items;
     if (items > 0xffffffffll)
       return fail(ctx, WL_EINVAL, "batch of %lld work items is too large", (long long)items);
-    const size_t desc_b = (d.size() * sizeof(wl::ReqDesc) + 255) & ~(size_t)255;
-    const size_t total_b = desc_b + 8 * (size_t)(grid_n + part_n + sums_n + 2 * pts_n);
-    if ((rc = ensure(ctx, &ctx->d_batch, &ctx->batch_bytes, total_b, "batch buffer"))) return rc;
-    char* base = (char*)ctx->d_batch;
-    double* d_grid = (double*)(base + desc_b);
-    double* d_part = d_grid + grid_n;
-    double* d_sums = d_part + part_n;
-    double* d_mean = d_sums + sums_n;
-    double* d_err = d_mean + pts_n;
-    std::vector<double> h_grid((size_t)grid_n);
-    for (size_t i = 0; i < d.size(); ++i) {
-      const wl_request& q = reqs[who[i]];
-      const int64_t go = (int64_t)(intptr_t)d[i].rho;
-      memcpy(&h_grid[go], q.rho, q.n_rho * sizeof(double));
-      memcpy(&h_grid[go + q.n_rho], q.T, q.n_T * sizeof(double));
-      d[i].rho = d_grid + go;
-      d[i].T = d_grid + go + q.n_rho;
-      const int64_t po = (int64_t)(intptr_t)d[i].out;
-      d[i].out = po >= 0 ? d_part + po : d_sums + d[i].sums_begin;
-    }
-    hipError_t e = hipMemcpyAsync(base, d.data(), d.size() * sizeof(wl::ReqDesc),
-                                  hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_grid, h_grid.data(), grid_n * sizeof(double),
-                         hipMemcpyHostToDevice, ctx->stream);
-    const int64_t want_wg = (items + wl::kWavesPerWG - 1) / wl::kWavesPerWG;
+    in_b = (in_b + 255) & ~(size_t)255;
+    if ((rc = ensure(ctx, &ctx->d_batch, &ctx->batch_bytes, in_b + res_b, "batch buffer")))
+      return rc;
+    void* d_in = ctx->d_batch;
+    double* d_res = (double*)((char*)ctx->d_batch + in_b);
+    std::vector<char> h_in(in_b);
+    wl::BatchLayout lay;
+    if (!build_batch(ens, rq.data(), rf.data(), pl.data(), (int32_t)rq.size(), h_in.data(),
+                     in_b, d_in, d_res, res_b, &lay))
+      return fail(ctx, WL_EINVAL, "internal: batch layout exceeds its buffer");
+    const int64_t want_wg = (lay.items + kWavesPerWG - 1) / kWavesPerWG;
     const int64_t max_wg = (int64_t)ctx->num_cu * 8;
+    hipError_t e = hipMemcpyAsync(d_in, h_in.data(), lay.in_bytes, hipMemcpyHostToDevice,
+                                  ctx->stream);
     if (e == hipSuccess)
-      e = wl::launch_batch(prec, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl,
-                           (const wl::ReqDesc*)base, (int32_t)d.size(), items, sums_n, pts_n,
-                           ens->n_groups, ens->n_loops, ens->n_loops / ens->n_groups,
-                           ctx->d_counter, d_sums, d_mean, d_err,
+      e = wl::launch_batch(prec, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl, d_in,
+                           ens->n_groups, ens->n_loops, ctx->d_counter, d_res,
                            (int32_t)(want_wg < max_wg ? want_wg : max_wg), ctx->stream);
-    std::vector<double> h_out((size_t)(sums_n + 2 * pts_n));
+    std::vector<double> h_res((size_t)(lay.sums_n + 2 * lay.pts_n));
     if (e == hipSuccess)
-      e = hipMemcpyAsync(h_out.data(), d_sums, h_out.size() * sizeof(double),
+      e = hipMemcpyAsync(h_res.data(), d_res, h_res.size() * sizeof(double),
                          hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "wl_average_batch");
-    for (size_t i = 0; i < d.size(); ++i) {
-      const wl_request& q = reqs[who[i]];
-      const int64_t n_pts = d[i].n_pts;
-      if (q.group_sums)
-        memcpy(q.group_sums, &h_out[d[i].sums_begin], G * n_pts * sizeof(double));
-      if (q.mean) memcpy(q.mean, &h_out[sums_n + d[i].pts_begin], n_pts * sizeof(double));
-      if (q.err)
-        memcpy(q.err, &h_out[sums_n + pts_n + d[i].pts_begin], n_pts * sizeof(double));
-    }
+    for (size_t i = 0; i < rq.size(); ++i)
+      scatter_results(*rq[i], lay, (int32_t)i, h_res.data(), ens->n_groups);
   }
   return WL_OK;
 }

@@ -45,6 +45,17 @@ struct FieldArgs {
   double cphi, cspin;
 };
 
+// Header of a batch in device memory, followed (at kBatchDescOffset) by
+// n_reqs ReqDesc.  The batch kernels read the counts from here, so one
+// captured launch sequence serves batches of any composition.
+struct BatchHeader {
+  int64_t n_reqs;
+  int64_t total_items;
+  int64_t total_sums;
+  int64_t total_pts;
+};
+constexpr size_t kBatchDescOffset = 64;
+
 // One request of a batched evaluation (device-resident descriptor).
 struct ReqDesc {
   FieldArgs f;
@@ -84,13 +95,15 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            int64_t n_loops, double* d_phase, double* d_spin,
                            double* d_w, hipStream_t stream);
 
+// Batched evaluation: counter reset, persistent item kernel, sub-range
+// reduction and statistics, all reading `d_hdr` (BatchHeader followed by
+// the descriptors).  Results at d_res: [group sums | means | errors |
+// partials] with the sizes from the header.  Grid sizes are fixed (n_wg
+// persistent workgroups), so the sequence can be captured once and replayed.
 hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
-                        const float* d_y, int32_t n_ppl, const ReqDesc* d_reqs,
-                        int32_t n_reqs, int64_t total_items, int64_t total_sums,
-                        int64_t total_pts, int32_t n_groups, int64_t n_loops,
-                        int64_t loops_per_group, unsigned int* d_counter,
-                        double* d_sums, double* d_mean, double* d_err,
-                        int32_t n_wg, hipStream_t stream);
+                        const float* d_y, int32_t n_ppl, const void* d_hdr,
+                        int32_t n_groups, int64_t n_loops, unsigned int* d_counter,
+                        double* d_res, int32_t n_wg, hipStream_t stream);
 
 hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,
                              int32_t n_sub, int32_t n_pts, double* d_sums,

@@ -402,9 +402,12 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
 template <int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_batch(
     const float4* __restrict__ seg, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl, const ReqDesc* __restrict__ reqs,
-    int32_t n_reqs, int64_t total_items, unsigned int* __restrict__ counter,
-    int64_t loops_per_group) {
+    const float* __restrict__ Y, int32_t n_ppl, const BatchHeader* __restrict__ hdr,
+    unsigned int* __restrict__ counter, int64_t loops_per_group) {
+  const ReqDesc* __restrict__ reqs =
+      (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
+  const int32_t n_reqs = (int32_t)hdr->n_reqs;
+  const int64_t total_items = hdr->total_items;
   const int32_t lane = threadIdx.x % kWave;
   for (;;) {
     unsigned int t = 0;
@@ -439,10 +442,13 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_batch(
 
 // Batched sub-range reduction and statistics: thread t handles output t of
 // the concatenation over requests (binary search for its request).
-__global__ __launch_bounds__(256) void k_reduce_batch(const ReqDesc* __restrict__ reqs,
-                                                      int32_t n_reqs, int64_t total,
-                                                      int32_t n_groups,
+// Result region of a batch: [group sums | means | errors | partials].
+__global__ __launch_bounds__(256) void k_reduce_batch(const BatchHeader* __restrict__ hdr,
                                                       double* __restrict__ sums) {
+  const ReqDesc* __restrict__ reqs =
+      (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
+  const int32_t n_reqs = (int32_t)hdr->n_reqs;
+  const int64_t total = hdr->total_sums;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = n_reqs - 1;
@@ -458,7 +464,6 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const ReqDesc* __restrict_
     for (int32_t s = 0; s < q.n_sub; ++s) acc += q.out[(g * q.n_sub + s) * q.n_pts + p];
     sums[t] = acc;
   }
-  (void)n_groups;
 }
 
 __device__ __forceinline__ void stats_point(const double* __restrict__ sums,
@@ -477,12 +482,16 @@ __device__ __forceinline__ void stats_point(const double* __restrict__ sums,
   e = n_groups > 1 ? sqrt(ss / ((double)n_groups * (n_groups - 1))) : NAN;
 }
 
-__global__ __launch_bounds__(256) void k_stats_batch(const ReqDesc* __restrict__ reqs,
-                                                     int32_t n_reqs, int64_t total_pts,
+__global__ __launch_bounds__(256) void k_stats_batch(const BatchHeader* __restrict__ hdr,
                                                      int32_t n_groups, int64_t n_loops,
-                                                     const double* __restrict__ sums,
-                                                     double* __restrict__ mean,
-                                                     double* __restrict__ err) {
+                                                     double* __restrict__ res) {
+  const ReqDesc* __restrict__ reqs =
+      (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
+  const int32_t n_reqs = (int32_t)hdr->n_reqs;
+  const int64_t total_pts = hdr->total_pts;
+  const double* __restrict__ sums = res;
+  double* __restrict__ mean = res + hdr->total_sums;
+  double* __restrict__ err = mean + total_pts;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total_pts;
        t += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = n_reqs - 1;
@@ -681,12 +690,11 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
 }
 
 hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
-                        const float* d_y, int32_t n_ppl, const ReqDesc* d_reqs,
-                        int32_t n_reqs, int64_t total_items, int64_t total_sums,
-                        int64_t total_pts, int32_t n_groups, int64_t n_loops,
-                        int64_t loops_per_group, unsigned int* d_counter,
-                        double* d_sums, double* d_mean, double* d_err,
-                        int32_t n_wg, hipStream_t stream) {
+                        const float* d_y, int32_t n_ppl, const void* d_hdr,
+                        int32_t n_groups, int64_t n_loops, unsigned int* d_counter,
+                        double* d_res, int32_t n_wg, hipStream_t stream) {
+  const BatchHeader* hdr = (const BatchHeader*)d_hdr;
+  const int64_t lpg = n_loops / n_groups;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, stream, d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -694,28 +702,24 @@ hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
   switch (precision) {
     case 0:
       hipLaunchKernelGGL((k_batch<0>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
-                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+                         hdr, d_counter, lpg);
       break;
     case 1:
       hipLaunchKernelGGL((k_batch<1>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
-                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+                         hdr, d_counter, lpg);
       break;
     case 2:
       hipLaunchKernelGGL((k_batch<2>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
-                         d_reqs, n_reqs, total_items, d_counter, loops_per_group);
+                         hdr, d_counter, lpg);
       break;
     default:
       return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t rb = (total_sums + 255) / 256;
-  hipLaunchKernelGGL(k_reduce_batch, dim3((uint32_t)(rb < 8192 ? rb : 8192)), dim3(256), 0,
-                     stream, d_reqs, n_reqs, total_sums, n_groups, d_sums);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(2048), dim3(256), 0, stream, hdr, d_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t sb = (total_pts + 255) / 256;
-  hipLaunchKernelGGL(k_stats_batch, dim3((uint32_t)(sb < 8192 ? sb : 8192)), dim3(256), 0,
-                     stream, d_reqs, n_reqs, total_pts, n_groups, n_loops, d_sums, d_mean,
-                     d_err);
+  hipLaunchKernelGGL(k_stats_batch, dim3(2048), dim3(256), 0, stream, hdr, n_groups, n_loops,
+                     d_res);
   return hipGetLastError();
 }
 

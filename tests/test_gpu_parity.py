@@ -268,3 +268,42 @@ def test_batch_equals_alone(wl, ctx):
                     *mean_scales(o["w"], o["spin"], 8))
     finally:
         wl.wl_ensemble_free(ens)
+
+
+def test_server_results_equal_alone(wl, ctx):
+    """Continuous batching: requests submitted to the server (several
+    batches, graph replays on two slots) give exactly wl_average's result for
+    each request alone; a request larger than a slot's budget is refused."""
+    say("server")
+    x, y = wlinputs.polygon_loops(512, 203, seed=29)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 8)
+    try:
+        reqs = wlinputs.draw_requests(24, seed=3)
+        for i, q in enumerate(reqs):
+            q["precision"] = (0, 0, 2)[i % 3]
+            q["rho"] = q["rho"][: 1 + i % 9]
+            q["T"] = q["T"][: 1 + (3 * i) % 17]
+        # a small result budget forces several batches per slot
+        srv = wl.Server(ctx, ens, slots=2, max_batch=5, result_bytes=1 << 20)
+        try:
+            tickets = [srv.submit(q) for q in reqs]
+            for t in tickets:
+                st, lat = srv.wait(t, 120.0)
+                assert st == 0 and lat >= 0
+            info = srv.info()
+            assert info["batches"] >= 5 and info["pending"] == 0
+            for q, t in zip(reqs, tickets):
+                m, e, s_ = srv.result(t)
+                m1, e1, s1 = wl.wl_average(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
+                                           q["rho"], q["T"], q["spin"], q["precision"])
+                assert np.array_equal(s_, s1) and np.array_equal(m, m1)
+                assert np.array_equal(e, e1, equal_nan=True)
+            big = dict(kind=1, eB0=1.0, lam=1.0, rho=np.linspace(0, 3, 128),
+                       T=np.geomspace(1e-3, 10, 64), spin=1, precision=0)
+            with pytest.raises(wl.WLError) as ei:
+                srv.submit(big)
+            assert ei.value.code == wl.WL_ENOMEM
+        finally:
+            srv.close()
+    finally:
+        wl.wl_ensemble_free(ens)

@@ -31,6 +31,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "wl_internal.h"
 #include "wl_poly.h"
 
@@ -66,7 +68,10 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 //   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
 //   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
 // r2 > 0 (the caller adds 1e-30).
-template <int KIND, bool COMP>
+// BR selects the near-axis handling of sech^2 and Gaussian fields: 0 = per
+// lane (branch on rho^2 < thr), 1 = every lane is far (closed form only),
+// 2 = every lane is near (polynomial only).
+template <int KIND, bool COMP, int BR = 0>
 __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
                                           float& qa, float& qb) {
   if constexpr (KIND == kConst) {
@@ -85,13 +90,23 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     const float ip = __builtin_amdgcn_rcpf(opE);
     const float Eip = E * ip;
     qb = Eip * ip;
-    if (r2 < f.thr) {
+    auto near = [&] {
       const float v = r2 * f.inv_lam2;
-      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
-    } else {
+      return horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
+    };
+    auto far = [&] {
       const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
       const float h = fmaf(-kLn2f, lg, kLn2f) - (rho * f.two_inv_lam) * Eip;
-      qa = (h * rs) * rs;
+      return (h * rs) * rs;
+    };
+    if constexpr (BR == 1) {
+      qa = far();
+    } else if constexpr (BR == 2) {
+      qa = near();
+    } else if (r2 < f.thr) {
+      qa = near();
+    } else {
+      qa = far();
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
@@ -99,11 +114,19 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     const float E = __builtin_amdgcn_exp2f(
         COMP ? fmaf(r2, f.exp2_scale, r2 * f.exp2_scale_lo) : r2 * f.exp2_scale);
     qb = E;
-    if (r2 < f.thr) {
+    auto near = [&] {
       const float v = r2 * f.inv_lam2;
-      qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
+      return horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
+    };
+    auto far = [&] { return (1.0f - E) * __builtin_amdgcn_rcpf(r2); };
+    if constexpr (BR == 1) {
+      qa = far();
+    } else if constexpr (BR == 2) {
+      qa = near();
+    } else if (r2 < f.thr) {
+      qa = near();
     } else {
-      qa = (1.0f - E) * __builtin_amdgcn_rcpf(r2);
+      qa = far();
     }
   } else {  // kRational
     const float r = __builtin_amdgcn_rcpf(COMP ? (r2 + f.lam2) + f.lam2_lo : r2 + f.lam2);
@@ -214,17 +237,35 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               const FieldArgs& f, double& A,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
+  constexpr bool kNearBranch = KIND == kSech2 || KIND == kGauss;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y, d_y, c)
+  // midpoint radius^2 and cross product of one segment,
+  // s = (m_x, m_y, d_y, c)
+  auto geom = [&](const float4 s, float& r2, float& cr) {
     const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
                           : fmaf(c.s_hi, s.x, c.rho_hi);
     const float my = c.s_hi * s.y;
-    const float r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
-    const float cr = fmaf(c.R, s.w, c.U * s.z);
-    float qa, qb;
+    r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
+    cr = fmaf(c.R, s.w, c.U * s.z);
+  };
+  auto term = [&](const float4 s, float& pa, float& pb) {
+    float r2, cr, qa, qb;
+    geom(s, r2, cr);
     field_f32<KIND, COMP>(r2, f, qa, qb);
     pa = fmaf(cr, qa, pa);
     if constexpr (kSpinSum) pb += qb;
+  };
+  // 8 segments whose near/far side is the same on every lane: straight-line
+  // code that the compiler can interleave across the 8 segments
+  auto block_uniform = [&](const float* r2v, const float* crv, auto br, float& pa,
+                           float& pb) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float qa, qb;
+      field_f32<KIND, COMP, decltype(br)::value>(r2v[k], f, qa, qb);
+      pa = fmaf(crv[k], qa, pa);
+      if constexpr (kSpinSum) pb += qb;
+    }
   };
   int32_t i = 0;
   for (; i + 8 <= n; i += 8) {
@@ -232,15 +273,40 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
     float4 sv[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
-    if constexpr (COMP) {
-      float pa = 0.0f, pb = 0.0f;
+    float pa = 0.0f, pb = 0.0f;
+    if constexpr (kNearBranch) {
+      float r2v[8], crv[8];
+      bool any_near = false, all_near = true;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        geom(sv[k], r2v[k], crv[k]);
+        const bool nr = r2v[k] < f.thr;
+        any_near |= nr;
+        all_near &= nr;
+      }
+      if (!__any(any_near)) {
+        block_uniform(r2v, crv, std::integral_constant<int, 1>(), pa, pb);
+      } else if (__all(all_near)) {
+        block_uniform(r2v, crv, std::integral_constant<int, 2>(), pa, pb);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          float qa, qb;
+          field_f32<KIND, COMP>(r2v[k], f, qa, qb);
+          pa = fmaf(crv[k], qa, pa);
+          if constexpr (kSpinSum) pb += qb;
+        }
+      }
+    } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
+    }
+    if constexpr (COMP) {
       kahan_add(as, ac, pa);
       if constexpr (kSpinSum) kahan_add(bs, bc, pb);
     } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) term(sv[k], as, bs);
+      as += pa;
+      bs += pb;
     }
   }
   if (i < n) {

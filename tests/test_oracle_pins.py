@@ -326,3 +326,16 @@ def test_small_T_series_printed_in_paper():
         r2 = integrand(part, 0.1) - series(part, 0.1)
         assert r2 / r1 == pytest.approx(32.0, rel=0.1), part
         assert abs(r1) < 1e-6 * abs(series(part, 0.05))
+
+
+def test_phase_conditioning_output():
+    """phase_abs is the sum of |segment phases|: >= |Phi|, equal to it for
+    a convex loop around the axis in a field of one sign (all terms share
+    a sign), and much larger off axis where the terms cancel."""
+    n = 64
+    a = 2 * np.pi * np.arange(n) / n
+    x, y = np.cos(a)[None], np.sin(a)[None]
+    o = oracle.evaluate(x, y, SECH2, 1.0, 1.0, np.array([0.0, 6.0]), np.array([1.0]), 0, 1,
+                        per_loop=True)
+    assert o["phase_abs"][0, 0, 0] == pytest.approx(abs(o["phase"][0, 0, 0]), rel=1e-12)
+    assert o["phase_abs"][0, 1, 0] > 50 * abs(o["phase"][0, 1, 0])

@@ -145,7 +145,7 @@ wl::Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts) {
   n_sub = (s.loops_per_group + s.loops_per_sub - 1) / s.loops_per_sub;
   s.n_sub = (int32_t)n_sub;
   s.n_items = base * n_sub;
-  s.n_wg = (int32_t)((s.n_items + wl::kWavesPerWG - 1) / wl::kWavesPerWG);
+  s.n_wg = 0;  // set by the launcher (workgroup size depends on precision)
   s.n_xcd = 8;  // MI355X: 8 XCDs; workgroups are dealt round-robin
   return s;
 }

@@ -24,7 +24,7 @@ struct Sched {
   int32_t n_sub;            // sub-ranges per group
   int32_t n_chunks;         // ceil(n_pts / 64)
   int64_t n_items;          // G * n_sub * n_chunks
-  int32_t n_wg;             // ceil(n_items / waves per workgroup)
+  int32_t n_wg;             // workgroups (set by the launcher)
   int32_t n_xcd;            // XCDs the dispatcher round-robins over
 };
 
@@ -71,7 +71,10 @@ struct ReqDesc {
   int32_t spin, pad;
 };
 
-constexpr int kWavesPerWG = 4;
+constexpr int kWavesPerWG = 4;  // batch and per-loop kernels
+// k_average: waves per workgroup (barrier-coupled), by precision; the FP64
+// kernel needs ~140 VGPRs, so smaller workgroups keep 3 waves per SIMD.
+constexpr int avg_waves(int prec) { return prec == 2 ? 4 : 8; }
 constexpr int kWave = 64;
 
 // Launchers (wl_kernels.hip).  All enqueue on `stream` and return the HIP

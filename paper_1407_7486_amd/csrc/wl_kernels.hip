@@ -31,8 +31,6 @@
 #include <math.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "wl_internal.h"
 #include "wl_poly.h"
 
@@ -68,10 +66,7 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 //   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
 //   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
 // r2 > 0 (the caller adds 1e-30).
-// BR selects the near-axis handling of sech^2 and Gaussian fields: 0 = per
-// lane (branch on rho^2 < thr), 1 = every lane is far (closed form only),
-// 2 = every lane is near (polynomial only).
-template <int KIND, bool COMP, int BR = 0>
+template <int KIND, bool COMP>
 __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
                                           float& qa, float& qb) {
   if constexpr (KIND == kConst) {
@@ -90,23 +85,13 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     const float ip = __builtin_amdgcn_rcpf(opE);
     const float Eip = E * ip;
     qb = Eip * ip;
-    auto near = [&] {
+    if (r2 < f.thr) {
       const float v = r2 * f.inv_lam2;
-      return horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
-    };
-    auto far = [&] {
+      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
+    } else {
       const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
       const float h = fmaf(-kLn2f, lg, kLn2f) - (rho * f.two_inv_lam) * Eip;
-      return (h * rs) * rs;
-    };
-    if constexpr (BR == 1) {
-      qa = far();
-    } else if constexpr (BR == 2) {
-      qa = near();
-    } else if (r2 < f.thr) {
-      qa = near();
-    } else {
-      qa = far();
+      qa = (h * rs) * rs;
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
@@ -114,19 +99,11 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     const float E = __builtin_amdgcn_exp2f(
         COMP ? fmaf(r2, f.exp2_scale, r2 * f.exp2_scale_lo) : r2 * f.exp2_scale);
     qb = E;
-    auto near = [&] {
+    if (r2 < f.thr) {
       const float v = r2 * f.inv_lam2;
-      return horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
-    };
-    auto far = [&] { return (1.0f - E) * __builtin_amdgcn_rcpf(r2); };
-    if constexpr (BR == 1) {
-      qa = far();
-    } else if constexpr (BR == 2) {
-      qa = near();
-    } else if (r2 < f.thr) {
-      qa = near();
+      qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
     } else {
-      qa = far();
+      qa = (1.0f - E) * __builtin_amdgcn_rcpf(r2);
     }
   } else {  // kRational
     const float r = __builtin_amdgcn_rcpf(COMP ? (r2 + f.lam2) + f.lam2_lo : r2 + f.lam2);
@@ -237,35 +214,17 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               const FieldArgs& f, double& A,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
-  constexpr bool kNearBranch = KIND == kSech2 || KIND == kGauss;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  // midpoint radius^2 and cross product of one segment,
-  // s = (m_x, m_y, d_y, c)
-  auto geom = [&](const float4 s, float& r2, float& cr) {
+  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y, d_y, c)
     const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
                           : fmaf(c.s_hi, s.x, c.rho_hi);
     const float my = c.s_hi * s.y;
-    r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
-    cr = fmaf(c.R, s.w, c.U * s.z);
-  };
-  auto term = [&](const float4 s, float& pa, float& pb) {
-    float r2, cr, qa, qb;
-    geom(s, r2, cr);
+    const float r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
+    const float cr = fmaf(c.R, s.w, c.U * s.z);
+    float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
     pa = fmaf(cr, qa, pa);
     if constexpr (kSpinSum) pb += qb;
-  };
-  // 8 segments whose near/far side is the same on every lane: straight-line
-  // code that the compiler can interleave across the 8 segments
-  auto block_uniform = [&](const float* r2v, const float* crv, auto br, float& pa,
-                           float& pb) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      float qa, qb;
-      field_f32<KIND, COMP, decltype(br)::value>(r2v[k], f, qa, qb);
-      pa = fmaf(crv[k], qa, pa);
-      if constexpr (kSpinSum) pb += qb;
-    }
   };
   int32_t i = 0;
   for (; i + 8 <= n; i += 8) {
@@ -273,40 +232,15 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
     float4 sv[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
-    float pa = 0.0f, pb = 0.0f;
-    if constexpr (kNearBranch) {
-      float r2v[8], crv[8];
-      bool any_near = false, all_near = true;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        geom(sv[k], r2v[k], crv[k]);
-        const bool nr = r2v[k] < f.thr;
-        any_near |= nr;
-        all_near &= nr;
-      }
-      if (!__any(any_near)) {
-        block_uniform(r2v, crv, std::integral_constant<int, 1>(), pa, pb);
-      } else if (__all(all_near)) {
-        block_uniform(r2v, crv, std::integral_constant<int, 2>(), pa, pb);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          float qa, qb;
-          field_f32<KIND, COMP>(r2v[k], f, qa, qb);
-          pa = fmaf(crv[k], qa, pa);
-          if constexpr (kSpinSum) pb += qb;
-        }
-      }
-    } else {
+    if constexpr (COMP) {
+      float pa = 0.0f, pb = 0.0f;
 #pragma unroll
       for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
-    }
-    if constexpr (COMP) {
       kahan_add(as, ac, pa);
       if constexpr (kSpinSum) kahan_add(bs, bc, pb);
     } else {
-      as += pa;
-      bs += pb;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) term(sv[k], as, bs);
     }
   }
   if (i < n) {
@@ -444,19 +378,57 @@ __device__ __forceinline__ void run_item(
 }
 
 // ------------------------------------------------------------- kernels
+// One workgroup = avg_waves(PREC) consecutive items, normally chunks of one
+// (group, sub-range): they walk the same loops, and a barrier after every
+// loop keeps them in step so that a loop's segments are fetched from HBM
+// about once per workgroup and then served from the caches.  Every wave,
+// including padding waves past the last item, runs the same
+// loops_per_sub barrier iterations.
 template <int KIND, bool SPIN, int PREC>
-__global__ __launch_bounds__(kWavesPerWG * kWave) void k_average(
+__global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
     const float4* __restrict__ seg, const float* __restrict__ X,
     const float* __restrict__ Y, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,
     double* __restrict__ out) {
   const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * kWavesPerWG + wave;
-  if (item >= sc.n_items) return;
-  run_item<KIND, SPIN, PREC>(seg, X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f,
-                             sc.loops_per_group, sc.loops_per_sub, sc.n_sub,
-                             sc.n_chunks, item, out);
+  const int32_t lane = threadIdx.x % kWave;
+  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * avg_waves(PREC) + wave;
+  const bool live = item < sc.n_items;
+  const int64_t it = live ? item : 0;
+  const int32_t chunk = (int32_t)(it % sc.n_chunks);
+  const int64_t gs = it / sc.n_chunks;  // g * n_sub + sub
+  const int64_t g = gs / sc.n_sub;
+  const int64_t sub = gs % sc.n_sub;
+  const int64_t l0 = g * sc.loops_per_group + sub * sc.loops_per_sub;
+  int64_t l1 = l0 + sc.loops_per_sub;
+  const int64_t gend = (g + 1) * sc.loops_per_group;
+  if (l1 > gend) l1 = gend;
+  if (!live) l1 = l0;
+
+  const int32_t p = chunk * kWave + lane;
+  const bool valid = live && p < n_pts;
+  const int32_t pp = p < n_pts ? p : n_pts - 1;
+  const double rho = rho_g[pp / n_T];
+  const double T = T_g[pp % n_T];
+  const double s = sqrt(T);
+  const LaneF32 c = lane_consts(rho, s, T);
+
+  double acc = 0.0;
+  for (int64_t k = 0; k < sc.loops_per_sub; ++k) {
+    const int64_t l = l0 + k;
+    if (l < l1) {
+      double A, B, phi, S;
+      if constexpr (PREC == 2) {
+        loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+      } else {
+        loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
+      }
+      acc += epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
+    }
+    __syncthreads();
+  }
+  if (valid) out[gs * n_pts + p] = acc;
 }
 
 // Batched evaluation of uneven requests in one persistent launch.  Items of
@@ -671,9 +643,11 @@ template <int KIND, bool SPIN, int PREC>
 hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const float* X,
                         const float* Y, int32_t n_ppl, const double* rho,
                         const double* T, int32_t n_T, int32_t n_pts,
-                        const Sched& s, double* out, hipStream_t st) {
+                        const Sched& s0, double* out, hipStream_t st) {
+  Sched s = s0;
+  s.n_wg = (int32_t)((s.n_items + avg_waves(PREC) - 1) / avg_waves(PREC));
   hipLaunchKernelGGL((k_average<KIND, SPIN, PREC>), dim3(s.n_wg),
-                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
+                     dim3(avg_waves(PREC) * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
                      n_T, n_pts, f, s, out);
   return hipGetLastError();
 }

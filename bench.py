@@ -106,6 +106,39 @@ def serve_run(wl, ctx, args):
     return out
 
 
+def batch_run(args):
+    """Uneven requests (sech^2 or Gaussian tube, eB0 ~ U[0.5,10], lambda ~
+    U[0.2,5], N_rho ~ U{4..128}, N_T ~ U{8..64}, spin 50/50, FP32C; seed 1)
+    evaluated by one wl_average_batch call (one persistent launch) on the
+    workload's ensemble."""
+    import torch
+
+    import paper_1407_7486_amd as wl
+    import wlinputs
+    cfg = wlinputs.WORKLOADS[args.workload]
+    x, y = wlinputs.dloop_ensemble(cfg["n_loops"], cfg["n_ppl"], seed=cfg["seed"])
+    ctx = wl.wl_create(0, torch.cuda.current_stream().cuda_stream)
+    ens = wl.wl_ensemble_upload(ctx, x, y, cfg["n_groups"])
+    del x, y
+    reqs = wlinputs.draw_requests(args.batch_requests, seed=1)
+    for q in reqs:
+        q["precision"] = wl.WL_FP32C
+    segs = sum(q["rho"].size * q["T"].size for q in reqs) * cfg["n_loops"] * cfg["n_ppl"]
+    log(f"[bench] batch: {len(reqs)} requests, {segs:.3e} segment evaluations")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = wl.wl_average_batch(ctx, ens, reqs)
+    dt = time.perf_counter() - t0
+    ok = all(bool((m == m).all()) for m, _, _ in outs)  # no NaN
+    wl.wl_ensemble_free(ens)
+    wl.wl_destroy(ctx)
+    out = {"batch": {"requests": len(reqs), "workload": args.workload,
+                     "segment_evals": segs, "wall_s": dt, "segment_evals_per_s": segs / dt,
+                     "finite": ok, "launches": 1}}
+    log(f"[bench] batch {segs / dt:.4e} seg/s in {dt:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +154,11 @@ def main():
                     help="Poisson arrival rate of the serving run, requests/s")
     ap.add_argument("--serve-loops", type=int, default=16384,
                     help="loops of the serving ensemble (4096 points each)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving run (prints its JSON) and exit")
+    ap.add_argument("--batch-requests", type=int, default=0,
+                    help="only a batched evaluation of this many uneven requests "
+                         "(request seed 1) on the workload's ensemble, then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes "
                          "(5 times; reference for HBM traffic counters) and exit")
@@ -132,6 +170,17 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU split is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.serve_only:
+        import torch
+
+        import paper_1407_7486_amd as wl
+        ctx = wl.wl_create(0, torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"serve": serve_run(wl, ctx, args)}), flush=True)
+        wl.wl_destroy(ctx)
+        return
+    if args.batch_requests:
+        batch_run(args)
+        return
 
     import numpy as np
     import torch
@@ -221,6 +270,23 @@ def main():
                "sample": f"first {nl} loops of the ensemble, full {rho.size}x{T.size} grid, "
                          f"FP64, {dtc:.1f} s wall"}
         log(f"[bench] cpu oracle {segs / dtc:.4e} seg/s on {cpu['cores']} threads")
+        # the constant-field scalar workload timed in full on the oracle
+        c1 = wlinputs.WORKLOADS["const_scalar_1k"]
+        xc, yc = wlinputs.dloop_ensemble(c1["n_loops"], c1["n_ppl"], seed=c1["seed"])
+        rc_, tc_ = wlinputs.rho_grid(*c1["rho"]), wlinputs.t_grid(*c1["T"])
+        t0 = time.perf_counter()
+        oc = oracle.evaluate(xc, yc, c1["kind"], c1["eB0"], c1["lam"], rc_, tc_, c1["spin"],
+                             c1["n_groups"], n_threads=0)
+        dtc1 = time.perf_counter() - t0
+        mc, ec, _ = oracle.stats(oc["group_sums"], c1["n_loops"])
+        wn = oracle.w_scalar_finite_n(tc_, c1["n_ppl"])
+        cpu["const_scalar_1k"] = {
+            "seconds": dtc1, "threads": oracle.max_threads(),
+            "segment_evals": c1["n_loops"] * c1["n_ppl"] * rc_.size * tc_.size,
+            "max_dev_from_exact_finite_N_in_group_errors": float(np.max(np.abs(mc - wn) / ec)),
+            "max_abs_dev_from_eBT_over_sinh": float(np.max(np.abs(
+                mc - oracle.w_scalar_continuum(c1["eB0"] * tc_))))}
+        log(f"[bench] cpu oracle constant-field workload {dtc1:.2f} s")
 
     wl.wl_ensemble_free(ens)
     serve = None

@@ -337,3 +337,38 @@ def test_constant_field_workload_against_closed_forms(wl, ctx):
         assert np.all(np.abs(np.log(wn / cont) - T ** 2 / (2 * cfg["n_ppl"])) < 1e-3)
     finally:
         wl.wl_ensemble_free(ens)
+
+
+def test_maximum_size_sampled(wl, ctx):
+    """The largest ensemble of the workloads (131072 loops x 8192 points:
+    8 GiB of coordinates, 16 GiB of derived segment data): a sampled grid
+    in both precisions, per-loop values at the first, a middle and the last
+    loop against the oracle, and group sums at sampled groups."""
+    say("maximum size 131072 x 8192")
+    nl, n, G = 131072, 8192, 64
+    x, y = wlinputs.dloop_ensemble(nl, n, seed=0)
+    ens = wl.wl_ensemble_upload(ctx, x, y, G)
+    try:
+        rho = np.array([0.0, 1.3, 4.2])
+        T = np.array([1e-3, 0.7, 12.0, 40.0])
+        fld = wl.field(1, 5.0, 1.0)
+        for prec in (0, 2):
+            m, e, s_ = wl.wl_average(ctx, ens, fld, rho, T, 1, prec)
+            assert np.isfinite(m).all()
+            for l in (0, 77777, nl - 1):
+                ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rho, T, 1, prec, l, 1)
+                o = oracle.evaluate(x[l:l + 1], y[l:l + 1], 1, 5.0, 1.0, rho, T, 1, 1,
+                                    per_loop=True)
+                check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1,
+                               o["phase_abs"], n)
+            per = nl // G
+            for g in (0, G - 1):
+                sl = slice(g * per, (g + 1) * per)
+                o = oracle.evaluate(x[sl], y[sl], 1, 5.0, 1.0, rho[1:2], T[1:2], 1, 1,
+                                    per_loop=True)
+                scale = (np.abs(o["w"]) * np.maximum(1.0, o["spin"])).sum()
+                tol = (1e-12 if prec == 2 else 1e-6) * scale
+                assert abs(s_[g, 1, 1] - o["group_sums"][0, 0, 0]) <= tol
+    finally:
+        wl.wl_ensemble_free(ens)
+        del x, y

@@ -13,6 +13,10 @@ Contents
   * closed forms      -- constant-field averages (Sec. 3.3): scalar
                          theta/sinh(theta), spinor theta*coth(theta), and the
                          exact finite-N scalar average of the discrete loop law.
+  * ``discretisation``-- the discretisation estimate of Sec. 4.1: three
+                         interleaved sub-loops, three levels of <W>, the
+                         parabolic extrapolation to N = infinity and its
+                         distance from the N-point level.
   * ``vloop_ensemble``-- an independent loop generator (i.i.d. Gaussian
                          increments, closed by subtracting their mean) that
                          samples the same discrete law as the d-loops of
@@ -184,6 +188,99 @@ def stats(group_sums, n_loops):
         err = np.full_like(mean, np.nan)
         jk = np.full_like(mean, np.nan)
     return mean, err, jk
+
+
+# ------------------------------------------------ discretisation estimate
+DISC_PAPER, DISC_FULL = 0, 1
+
+
+def subloops(x, y):
+    """The three interleaved sub-worldlines of Sec. 4.1 (one of N/2 points,
+    two of N/4): circle = points 0, 2, 4, ...; square = points 1, 5, 9, ...;
+    triangle = points 3, 7, 11, ...  Each keeps the parent loop's
+    coordinates (no re-centring), so all three sit at the same centre of
+    mass.  Requires N divisible by 4."""
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return ((x[..., 0::2], y[..., 0::2]), (x[..., 1::4], y[..., 1::4]),
+            (x[..., 3::4], y[..., 3::4]))
+
+
+def extrapolate(w_n, w_n2, w_n4):
+    """Parabola in 1/N through <W> at N, N/2 and N/4 points, evaluated at
+    1/N = 0 (Sec. 4.1): 8/3 W_N - 2 W_{N/2} + 1/3 W_{N/4}."""
+    return (8.0 * np.asarray(w_n) - 6.0 * np.asarray(w_n2) + np.asarray(w_n4)) / 3.0
+
+
+def discretisation(x, y, kind, eB0, lam, rho, T, spin, n_groups,
+                   mode=DISC_PAPER, nq=1, per_loop=False):
+    """Discretisation estimate of Sec. 4.1 over an ensemble.
+
+    Each sub-loop's line integral of A (its phase) and its spin exponent
+    (T/M) sum b over its M points come from ``evaluate`` applied to the
+    sub-polygon.  Per loop, with phases c, s, t and spin exponents Sc, Ss,
+    St of the circle, square and triangle sub-loops:
+
+      mode DISC_PAPER (the levels as Sec. 4.1 writes them)
+        W_N    = cos(c/2 + s/4 + t/4) cosh(Sc/2 + Ss/4 + St/4)
+        W_N/2  = cos(c) cosh(Sc)
+        W_N/4  = cos((s + t)/2) cosh((Ss + St)/2)
+      mode DISC_FULL
+        W_N    = the full N-point loop (what ``evaluate`` gives)
+        W_N/2  = cos(c) cosh(Sc)
+        W_N/4  = (cos(s) cosh(Ss) + cos(t) cosh(St)) / 2
+    (cosh factors only for spin = 1; the spin exponents are combined with
+    the weights of the phases).  Levels are summed over contiguous groups;
+    level 3 is the extrapolation 8/3 W_N - 2 W_N/2 + 1/3 W_N/4, formed group
+    by group, so its error is the standard error of its group means.
+
+    Returns ``group_sums`` (4, G, n_rho, n_T) and ``mean``, ``err`` (4,
+    n_rho, n_T) for the levels [N, N/2, N/4, extrapolated], and ``delta`` =
+    |W_N - W_extrapolated| (n_rho, n_T).  With ``per_loop``, also ``phase``
+    and ``spin`` (3, n_loops, n_rho, n_T) of the circle, square and
+    triangle sub-loops, and ``w`` (3, n_loops, n_rho, n_T) of the levels.
+    """
+    X = np.asarray(x, dtype=np.float64)
+    Y = np.asarray(y, dtype=np.float64)
+    n_loops, n = X.shape
+    if n % 4 != 0 or n < 8:
+        raise ValueError("sub-loops need N divisible by 4 and N >= 8")
+    if n_loops % n_groups != 0:
+        raise ValueError("n_groups must divide n_loops")
+    rho = np.asarray(rho, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    ph, sp = [], []
+    for sx, sy in subloops(X, Y):
+        o = evaluate(sx, sy, kind, eB0, lam, rho, T, spin, 1, nq=nq, per_loop=True)
+        ph.append(o["phase"])
+        sp.append(o["spin"] if spin else np.zeros_like(o["spin"]))
+    c, s, t = ph
+    sc, ss, st = sp
+    ch = np.cosh if spin else (lambda a: 1.0)
+    w2 = np.cos(c) * ch(sc)
+    if mode == DISC_PAPER:
+        w1 = np.cos(0.5 * c + 0.25 * s + 0.25 * t) * ch(0.5 * sc + 0.25 * ss + 0.25 * st)
+        w4 = np.cos(0.5 * (s + t)) * ch(0.5 * (ss + st))
+    elif mode == DISC_FULL:
+        w1 = evaluate(X, Y, kind, eB0, lam, rho, T, spin, 1, nq=nq, per_loop=True)["w"]
+        w4 = 0.5 * (np.cos(s) * ch(ss) + np.cos(t) * ch(st))
+    else:
+        raise ValueError("unknown mode")
+    G = n_groups
+    nr, nt = rho.size, T.size
+    gs = np.empty((4, G, nr, nt))
+    for k, w in enumerate((w1, w2, w4)):
+        gs[k] = np.asarray(w).reshape(G, n_loops // G, nr, nt).sum(axis=1)
+    gs[3] = extrapolate(gs[0], gs[1], gs[2])
+    mean = np.empty((4, nr, nt))
+    err = np.empty((4, nr, nt))
+    for k in range(4):
+        mean[k], err[k], _ = stats(gs[k], n_loops)
+    out = {"group_sums": gs, "mean": mean, "err": err,
+           "delta": np.abs(mean[0] - mean[3])}
+    if per_loop:
+        out.update(phase=np.stack(ph), spin=np.stack(sp), w=np.stack([w1, w2, w4]))
+    return out
 
 
 # ----------------------------------------------------------- closed forms

@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--workload", default="sech2_spinor_64k")
+    ap.add_argument("--disc-steps", type=int, default=1,
+                    help="timed calls of the discretisation estimate per mode (0: skip)")
     ap.add_argument("--cpu-loops", type=int, default=64,
                     help="loops in the oracle's timed CPU sample (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
@@ -248,6 +250,30 @@ def main():
                 "max_rel_mean_diff_fp32c_vs_fp64": float(np.max(np.abs(mean32 - mean64) / scale))}
         log(f"[bench] fp64 {v64:.4e} seg/s, kernel {k64:.1f} ms")
 
+    disc = None
+    if args.disc_steps > 0 and cfg["n_ppl"] % 4 == 0:
+        # discretisation estimate (three sub-loops, Sec. 4.1), FP32C; the
+        # paper mode walks N sub-loop segments per loop, the full-loop mode
+        # the whole loop as well (2N)
+        disc = {}
+        for mode, name, segs in ((wl.WL_DISC_PAPER, "paper", 1), (wl.WL_DISC_FULL, "full", 2)):
+            wl.wl_discretisation(ctx, ens, fld, rho, T, spin, wl.WL_FP32C, mode)  # warm-up
+            wl.wl_set_timing(ctx, True)
+            t0 = time.perf_counter()
+            for _ in range(args.disc_steps):
+                dm, de, dd, _ = wl.wl_discretisation(ctx, ens, fld, rho, T, spin, wl.WL_FP32C,
+                                                     mode)
+            dtd = time.perf_counter() - t0
+            kd, nd = wl.wl_kernel_ms_total(ctx)
+            wl.wl_set_timing(ctx, False)
+            evals = segs * seg_per_step * args.disc_steps
+            disc[name] = {"kernel_ms": kd / nd, "segment_evals_per_s": evals / (kd * 1e-3),
+                          "wall_s_per_call": dtd / args.disc_steps,
+                          "max_delta_over_err_N": float(np.max(dd / de[0])),
+                          "finite": bool(np.isfinite(dm).all())}
+            log(f"[bench] disc {name}: kernel {kd / nd:.1f} ms, "
+                f"{evals / (kd * 1e-3):.4e} seg/s")
+
     slots = SLOTS_FP32C[(kname, spin)]
     achieved = seg_per_step * slots / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
@@ -304,6 +330,7 @@ def main():
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
         "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "serve": serve,
+        "disc": disc,
     }
     print(json.dumps(out), flush=True)
 

@@ -252,9 +252,71 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                 int32_t spin, int32_t precision, int64_t loop0,
                 int64_t n_loops, double* phase, double* spin_exp, double* w);
 
+/* ---- discretisation estimate (Sec. 4.1, Estimating the Discretization
+ * Uncertainties) ---------------------------------------------------------
+ * Each loop's N points (N divisible by 4, N >= 8) form three interleaved
+ * sub-loops that keep the loop's own coordinates (no re-centring):
+ *   WL_SUB_CIRCLE    the N/2 points 0, 2, 4, ...
+ *   WL_SUB_SQUARE    the N/4 points 1, 5, 9, ...
+ *   WL_SUB_TRIANGLE  the N/4 points 3, 7, 11, ...
+ * A sub-loop of M points is evaluated as a closed loop of its own: phase by
+ * the midpoint rule over its M segments, spin exponent (T/M) times the sum
+ * of eB over its segment midpoints.  With c, s, t the three phases and Sc,
+ * Ss, St the spin exponents, each loop gives three levels of w:
+ *   WL_DISC_PAPER  (the combinations the paper writes down)
+ *     level N      cos(c/2 + s/4 + t/4) cosh(Sc/2 + Ss/4 + St/4)
+ *     level N/2    cos(c) cosh(Sc)
+ *     level N/4    cos((s + t)/2) cosh((Ss + St)/2)
+ *   WL_DISC_FULL
+ *     level N      the whole loop's w, as wl_average computes it
+ *     level N/2    cos(c) cosh(Sc)
+ *     level N/4    (cos(s) cosh(Ss) + cos(t) cosh(St)) / 2
+ * (cosh factors for spinors only).  Every term of WL_DISC_FULL is a loop of
+ * the discrete loop law at its own number of points, so its levels are
+ * averages over N-, N/2- and N/4-point loops; the paper's N and N/4 levels
+ * average correlated sub-loop phases instead, which narrows the phase
+ * distribution (for a constant field both lie above the finite-N averages).
+ * WL_DISC_PAPER walks each loop's N sub-loop segments once; WL_DISC_FULL
+ * walks the whole loop as well (twice the segment work).
+ * Level 3 is the parabola in 1/N through the three levels, evaluated at
+ * 1/N = 0: 8/3 W_N - 2 W_{N/2} + 1/3 W_{N/4}, formed group by group so that
+ * its error is the standard error of its group means; delta = |W_N - W_inf|
+ * is the paper's estimate of the discretisation uncertainty. */
+#define WL_DISC_PAPER 0
+#define WL_DISC_FULL 1
+
+#define WL_SUB_CIRCLE 0
+#define WL_SUB_SQUARE 1
+#define WL_SUB_TRIANGLE 2
+
+/* Discretisation estimate over the grid rho[n_rho] x T[n_T] (arguments as
+ * wl_average; mode WL_DISC_PAPER or WL_DISC_FULL).  Outputs (host,
+ * caller-owned, each may be NULL), levels in the order N, N/2, N/4,
+ * extrapolated:
+ *   mean       [4][n_rho][n_T]
+ *   err        [4][n_rho][n_T]     standard error of the group means
+ *   delta      [n_rho][n_T]        |mean[0] - mean[3]|
+ *   group_sums [4][G][n_rho][n_T]
+ * The first call with WL_FP32C or WL_FP32 on an ensemble derives its
+ * sub-loop segment array (16 bytes per point, freed with the ensemble).
+ * Synchronous; deterministic like wl_average.  Errors: WL_EINVAL (also for
+ * n_ppl not divisible by 4 or below 8), WL_ENOMEM, WL_EHIP. */
+int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                      const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                      int32_t spin, int32_t precision, int32_t mode, double* mean,
+                      double* err, double* delta, double* group_sums);
+
+/* As wl_per_loop, for one sub-loop (WL_SUB_*) of each loop: phase,
+ * spin exponent (T/M) sum eB and w of that sub-loop alone.  Same kernels
+ * and sub-loop data as wl_discretisation. */
+int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                        const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                        int32_t spin, int32_t precision, int32_t subloop, int64_t loop0,
+                        int64_t n_loops, double* phase, double* spin_exp, double* w);
+
 /* Kernel timing: when enabled, the main evaluation kernel of each
- * wl_average / wl_average_async call is bracketed by HIP events on the ctx
- * stream.  wl_set_timing(ctx, 1) also forgets earlier records.
+ * wl_average / wl_average_async / wl_discretisation call is bracketed by
+ * HIP events on the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.
  * wl_last_kernel_ms waits for the last recorded launch and returns its
  * duration in milliseconds; wl_kernel_ms_total waits for all of them and
  * returns the sum of their durations and their count.  Both return

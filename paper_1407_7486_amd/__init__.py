@@ -23,6 +23,8 @@ WL_OK, WL_EINVAL, WL_ENOMEM, WL_EHIP, WL_ENODEV = 0, -1, -2, -3, -4
 WL_CONST, WL_SECH2, WL_GAUSS, WL_RATIONAL = 0, 1, 2, 3
 WL_FP32C, WL_FP32, WL_FP64 = 0, 1, 2
 WL_HOST_PTR, WL_DEVICE_PTR = 0, 1
+WL_DISC_PAPER, WL_DISC_FULL = 0, 1
+WL_SUB_CIRCLE, WL_SUB_SQUARE, WL_SUB_TRIANGLE = 0, 1, 2
 
 # every entry point declared in include/wl.h
 EXPORTS = (
@@ -32,6 +34,7 @@ EXPORTS = (
     "wl_last_kernel_ms", "wl_kernel_ms_total", "wl_average_batch",
     "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
+    "wl_discretisation", "wl_subloop_per_loop",
 )
 
 
@@ -92,6 +95,10 @@ _sigs = {
                           _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "wl_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
                      _i32, _i32, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "wl_discretisation": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
+                           _i32, _i32, _i32, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "wl_subloop_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
+                             _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "wl_set_timing": ([_vp, _i32], ctypes.c_int),
     "wl_last_kernel_ms": ([_vp, ctypes.POINTER(_d)], ctypes.c_int),
     "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
@@ -209,6 +216,35 @@ def wl_average(ctx, ens, fld, rho, T, spin, precision=WL_FP32C):
                            _ptr(T), T.size, int(spin), int(precision),
                            _ptr(mean), _ptr(err), _ptr(sums)), ctx)
     return mean, err, sums
+
+
+def wl_discretisation(ctx, ens, fld, rho, T, spin, precision=WL_FP32C, mode=WL_DISC_PAPER):
+    """Discretisation estimate (levels N, N/2, N/4, extrapolated); returns
+    (mean, err, delta, group_sums) of shapes (4, n_rho, n_T), (4, n_rho,
+    n_T), (n_rho, n_T), (4, G, n_rho, n_T)."""
+    rho = _host_f64(rho)
+    T = _host_f64(T)
+    _, _, G = wl_ensemble_info(ens)
+    mean = np.zeros((4, rho.size, T.size))
+    err = np.zeros((4, rho.size, T.size))
+    delta = np.zeros((rho.size, T.size))
+    sums = np.zeros((4, G, rho.size, T.size))
+    _check(_lib.wl_discretisation(ctx, ens, ctypes.byref(fld), _ptr(rho), rho.size,
+                                  _ptr(T), T.size, int(spin), int(precision), int(mode),
+                                  _ptr(mean), _ptr(err), _ptr(delta), _ptr(sums)), ctx)
+    return mean, err, delta, sums
+
+
+def wl_subloop_per_loop(ctx, ens, fld, rho, T, spin, precision, subloop, loop0, n_loops):
+    """Per-loop (phase, spin_exp, w) of one sub-loop (WL_SUB_*), each of
+    shape (n_loops, n_rho, n_T)."""
+    rho = _host_f64(rho)
+    T = _host_f64(T)
+    out = [np.zeros((n_loops, rho.size, T.size)) for _ in range(3)]
+    _check(_lib.wl_subloop_per_loop(ctx, ens, ctypes.byref(fld), _ptr(rho), rho.size,
+                                    _ptr(T), T.size, int(spin), int(precision), int(subloop),
+                                    int(loop0), int(n_loops), *[_ptr(a) for a in out]), ctx)
+    return tuple(out)
 
 
 def wl_average_async(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,

@@ -366,6 +366,7 @@ int wl_ensemble_free(wl_ens* ens) {
   (void)hipFree(ens->d_x);
   (void)hipFree(ens->d_y);
   (void)hipFree(ens->d_seg);
+  if (ens->d_sub) (void)hipFree(ens->d_sub);
   delete ens;
   return WL_OK;
 }
@@ -611,6 +612,43 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
   return WL_OK;
 }
 
+// Sub-loop segment array of the discretisation estimate, derived once per
+// ensemble on the ctx stream.
+static int ensure_sub(wl_ctx* ctx, const wl_ens* ens) {
+  if (ens->d_sub) return WL_OK;
+  const int64_t npts = ens->n_loops * ens->n_ppl;
+  float4* d = nullptr;
+  if (hipMalloc((void**)&d, npts * sizeof(float4)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, WL_ENOMEM, "device allocation of the sub-loop segments (%lld bytes) failed",
+                (long long)(npts * (int64_t)sizeof(float4)));
+  }
+  hipError_t e = wl::launch_prep_sub(ens->d_x, ens->d_y, ens->n_loops, ens->n_ppl, d,
+                                     ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    return hip_fail(ctx, e, "sub-loop segments");
+  }
+  ens->d_sub = d;
+  return WL_OK;
+}
+
+static int check_subloops(wl_ctx* ctx, const wl_ens* ens) {
+  if (ens->n_ppl % 4 != 0 || ens->n_ppl < 8)
+    return fail(ctx, WL_EINVAL, "sub-loops need n_ppl divisible by 4 and >= 8 (have %d)",
+                ens->n_ppl);
+  return WL_OK;
+}
+
+// Per-loop values of the part of each loop that `sl` names (segments of
+// `seg` for the FP32 paths, strided raw points for FP64).
+static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
+                         const float4* seg, const wl::SubLoop& sl, const double* rho,
+                         int32_t n_rho, const double* T, int32_t n_T, int32_t spin,
+                         int32_t precision, int64_t loop0, int64_t n_loops, double* phase,
+                         double* spin_exp, double* w);
+
 int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                 const double* rho, int32_t n_rho, const double* T, int32_t n_T,
                 int32_t spin, int32_t precision, int64_t loop0, int64_t n_loops,
@@ -622,6 +660,46 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   wl::FieldArgs fa;
   if ((rc = check_field(ctx, field, &fa))) return rc;
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const wl::SubLoop sl{0, ens->n_ppl, 0, 1};
+  return per_loop_impl(ctx, ens, fa, ens->d_seg, sl, rho, n_rho, T, n_T, spin, precision,
+                       loop0, n_loops, phase, spin_exp, w);
+}
+
+int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                        const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                        int32_t spin, int32_t precision, int32_t subloop, int64_t loop0,
+                        int64_t n_loops, double* phase, double* spin_exp, double* w) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  int rc = check_common(ctx, ens, spin, precision);
+  if (rc) return rc;
+  wl::FieldArgs fa;
+  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
+  if ((rc = check_subloops(ctx, ens))) return rc;
+  const int32_t h = ens->n_ppl / 2, q = ens->n_ppl / 4;
+  wl::SubLoop sl;
+  switch (subloop) {
+    case WL_SUB_CIRCLE: sl = wl::SubLoop{0, h, 0, 2}; break;
+    case WL_SUB_SQUARE: sl = wl::SubLoop{h, q, 1, 4}; break;
+    case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q, 3, 4}; break;
+    default: return fail(ctx, WL_EINVAL, "unknown sub-loop %d", subloop);
+  }
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
+  return per_loop_impl(ctx, ens, fa, ens->d_sub, sl, rho, n_rho, T, n_T, spin, precision,
+                       loop0, n_loops, phase, spin_exp, w);
+}
+
+static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
+                         const float4* seg, const wl::SubLoop& sl, const double* rho,
+                         int32_t n_rho, const double* T, int32_t n_T, int32_t spin,
+                         int32_t precision, int64_t loop0, int64_t n_loops, double* phase,
+                         double* spin_exp, double* w) {
+  int rc;
   if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
     return fail(ctx, WL_EINVAL, "loop range [%lld, %lld) outside the ensemble",
                 (long long)loop0, (long long)(loop0 + n_loops));
@@ -629,8 +707,6 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if (n_pts == 0 || n_loops == 0) return WL_OK;
   if (n_loops * n_pts > ((int64_t)1 << 27))
     return fail(ctx, WL_EINVAL, "n_loops * grid points above 2^27 in one call");
-  DeviceGuard g(ctx->device);
-  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
   const size_t each = (size_t)(n_loops * n_pts);
   if ((rc = ensure(ctx, &ctx->d_grid, &ctx->grid_bytes, gbytes, "grid"))) return rc;
@@ -647,7 +723,7 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = wl::launch_per_loop(precision, spin, fa, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl,
+    e = wl::launch_per_loop(precision, spin, fa, seg, ens->d_x, ens->d_y, ens->n_ppl, sl,
                             d_rho, d_T, n_T, (int32_t)n_pts, loop0, n_loops, d_ph, d_sp, d_w,
                             ctx->stream);
   if (e == hipSuccess && phase)
@@ -658,7 +734,87 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if (e == hipSuccess && w)
     e = hipMemcpyAsync(w, d_w, each * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return hip_fail(ctx, e, "wl_per_loop");
+  if (e != hipSuccess) return hip_fail(ctx, e, "per-loop evaluation");
+  return WL_OK;
+}
+
+int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                      const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                      int32_t spin, int32_t precision, int32_t mode, double* mean,
+                      double* err, double* delta, double* group_sums) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  int rc = check_common(ctx, ens, spin, precision);
+  if (rc) return rc;
+  wl::FieldArgs fa;
+  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
+  if ((rc = check_subloops(ctx, ens))) return rc;
+  if (mode != WL_DISC_PAPER && mode != WL_DISC_FULL)
+    return fail(ctx, WL_EINVAL, "unknown discretisation mode %d", mode);
+  const int64_t n_pts = (int64_t)n_rho * n_T;
+  if (n_pts == 0) return WL_OK;
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
+  const int64_t G = ens->n_groups;
+  const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
+  const size_t sums_n = 4 * (size_t)G * n_pts;
+  const size_t obytes = (sums_n + 9 * (size_t)n_pts) * sizeof(double);
+  if ((rc = ensure(ctx, &ctx->d_grid, &ctx->grid_bytes, gbytes, "grid"))) return rc;
+  if ((rc = ensure(ctx, &ctx->d_out, &ctx->out_bytes, obytes, "results"))) return rc;
+  const wl::Sched s = make_sched(ctx, ens, (int32_t)n_pts);
+  double* level_out = nullptr;
+  if (s.n_sub > 1) {
+    const size_t need = 3 * (size_t)G * s.n_sub * n_pts * sizeof(double);
+    if ((rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "partial sums")))
+      return rc;
+    level_out = (double*)ctx->d_partial;
+  }
+  double* d_rho = (double*)ctx->d_grid;
+  double* d_T = d_rho + n_rho;
+  double* d_sums = (double*)ctx->d_out;
+  double* d_mean = d_sums + sums_n;
+  double* d_err = d_mean + 4 * n_pts;
+  double* d_delta = d_err + 4 * n_pts;
+  if (!level_out) level_out = d_sums;
+  hipError_t e = hipMemcpyAsync(d_rho, rho, n_rho * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (e == hipSuccess && ctx->timing) {
+    e = next_events(ctx, &ev0, &ev1);
+    if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
+  }
+  if (e == hipSuccess)
+    e = wl::launch_disc(precision, spin, fa, ens->d_seg, ens->d_sub, ens->d_x, ens->d_y,
+                        ens->n_ppl, d_rho, d_T, n_T, (int32_t)n_pts, s,
+                        mode == WL_DISC_FULL ? 1 : 0, level_out, ctx->stream);
+  if (e == hipSuccess && ctx->timing) {
+    e = hipEventRecord(ev1, ctx->stream);
+    if (e == hipSuccess) ctx->n_timed++;
+  }
+  if (e == hipSuccess && s.n_sub > 1)
+    e = wl::launch_reduce_sub(level_out, 3 * (int32_t)G, s.n_sub, (int32_t)n_pts, d_sums,
+                              ctx->stream);
+  if (e == hipSuccess)
+    e = wl::launch_disc_finish(d_sums, (int32_t)G, (int32_t)n_pts, ens->n_loops, d_mean,
+                               d_err, d_delta, ctx->stream);
+  if (e == hipSuccess && group_sums)
+    e = hipMemcpyAsync(group_sums, d_sums, sums_n * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && mean)
+    e = hipMemcpyAsync(mean, d_mean, 4 * n_pts * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && err)
+    e = hipMemcpyAsync(err, d_err, 4 * n_pts * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && delta)
+    e = hipMemcpyAsync(delta, d_delta, n_pts * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "wl_discretisation");
   return WL_OK;
 }
 

@@ -43,6 +43,9 @@ struct wl_ens {
   float* d_x = nullptr;
   float* d_y = nullptr;
   float4* d_seg = nullptr;
+  // sub-loop segment array of the discretisation estimate, derived on first
+  // use by an FP32 evaluation (same size as d_seg)
+  mutable float4* d_sub = nullptr;
 };
 
 namespace wl {

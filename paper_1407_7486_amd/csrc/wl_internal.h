@@ -28,6 +28,14 @@ struct Sched {
   int32_t n_xcd;            // XCDs the dispatcher round-robins over
 };
 
+// Which part of each loop a per-loop evaluation walks: m points, taken for
+// the FP32 paths as segments seg_off .. seg_off+m-1 of the loop's entries in
+// the segment array passed, for the FP64 path as points x_off + k*x_stride
+// of the raw coordinates.  Whole loop: {0, N, 0, 1} with the segment array.
+struct SubLoop {
+  int32_t seg_off, m, x_off, x_stride;
+};
+
 // Field constants prepared on the host for one launch.
 struct FieldArgs {
   int32_t kind;
@@ -92,11 +100,34 @@ hipError_t launch_average(int precision, int spin, const FieldArgs& f,
 
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            const float4* d_seg, const float* d_x,
-                           const float* d_y, int32_t n_ppl,
+                           const float* d_y, int32_t n_ppl, const SubLoop& sl,
                            const double* d_rho, const double* d_T,
                            int32_t n_T, int32_t n_pts, int64_t loop0,
                            int64_t n_loops, double* d_phase, double* d_spin,
                            double* d_w, hipStream_t stream);
+
+// Discretisation estimate (Sec. 4.1).  The sub-loop segment array holds,
+// per loop, the N/2 segments of the circle sub-loop (points 0, 2, 4, ...),
+// then the N/4 of the square one (1, 5, 9, ...) and the N/4 of the triangle
+// one (3, 7, 11, ...), in the per-segment format above.
+hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
+                           int32_t n_ppl, float4* d_sub, hipStream_t stream);
+
+// Level sums for levels N, N/2, N/4: d_out [3][G*n_sub][n_pts] (with
+// n_sub == 1 these are the group sums [3][G][n_pts]).  full != 0: the N
+// level is the whole loop instead of the paper's combination of sub-loops.
+hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
+                       const float4* d_sub, const float* d_x, const float* d_y,
+                       int32_t n_ppl, const double* d_rho, const double* d_T, int32_t n_T,
+                       int32_t n_pts, const Sched& s, int32_t full, double* d_out,
+                       hipStream_t stream);
+
+// d_sums [4][G][n_pts] with levels 0..2 filled: writes level 3 (the
+// extrapolation), the means and errors [4][n_pts] and delta [n_pts] (each
+// output may be NULL but d_sums).
+hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
+                              int64_t n_loops, double* d_mean, double* d_err,
+                              double* d_delta, hipStream_t stream);
 
 // Batched evaluation: counter reset, persistent item kernel, sub-range
 // reduction and statistics, all reading `d_hdr` (BatchHeader followed by

@@ -259,13 +259,15 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
 }
 
 // FP64 path: reads the raw FP32 unit coordinates (exact in FP64) and forms
-// the midpoint, step and cross product of every segment in FP64.
+// the midpoint, step and cross product of every segment in FP64.  The loop
+// is the closed polygon through X[k*stride], k = 0 .. n-1 (stride 1: the
+// whole loop; 2 or 4: an interleaved sub-loop).
 template <int KIND, bool SPIN>
 __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
                                               const float* __restrict__ Y,
-                                              int32_t n, double rho, double s,
-                                              const FieldArgs& f, double& A,
-                                              double& B) {
+                                              int32_t stride, int32_t n, double rho,
+                                              double s, const FieldArgs& f,
+                                              double& A, double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   double a = 0.0, b = 0.0;
   auto step = [&](float x0f, float y0f, float x1f, float y1f) {
@@ -283,7 +285,7 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
   float xp = X[0], yp = Y[0];
   int32_t i = 1;
   for (; i < n; ++i) {
-    const float xn = X[i], yn = Y[i];
+    const float xn = X[i * stride], yn = Y[i * stride];
     step(xp, yp, xn, yn);
     xp = xn;
     yp = yn;
@@ -299,28 +301,64 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
 // S log2(e), scaled by the integer part in FP64 (relative error ~1e-7, no
 // overflow below FP64's range); the FP64 path forms cosh from the library
 // exp.
+template <int PREC>
+__device__ __forceinline__ double cosh_spin(double S) {
+  if constexpr (PREC == 2) {
+    const double e = exp(fabs(S));
+    return 0.5 * (e + 1.0 / e);
+  } else {
+    const double t = fabs(S) * 1.4426950408889634074;  // |S| log2(e)
+    const double k = floor(t);
+    const float p = __builtin_amdgcn_exp2f((float)(t - k));  // 2^frac in [1,2)
+    const int ki = (int)fminf((float)k, 2000.0f);
+    return 0.5 * (ldexp((double)p, ki) + ldexp(1.0 / (double)p, -ki));
+  }
+}
+
+// w = cos(phi) (scalar) or cos(phi) cosh(S) (spinor).
+template <bool SPIN, int PREC>
+__device__ __forceinline__ double wval(double phi, double S) {
+  const double rev = phi * 0.15915494309189533577;
+  const double cw = cospi(2.0 * (rev - rint(rev)));
+  if constexpr (!SPIN) return cw;
+  else return cw * cosh_spin<PREC>(S);
+}
+
+// phi = cphi A, S = cspin (T/n) B for a loop of n points, and its w.
 template <bool SPIN, int PREC>
 __device__ __forceinline__ double epilogue(double A, double B, double T,
                                            int32_t n, const FieldArgs& f,
                                            double& phi, double& S) {
   phi = f.cphi * A;
-  const double rev = phi * 0.15915494309189533577;
-  const double cw = cospi(2.0 * (rev - rint(rev)));
-  if constexpr (!SPIN) {
-    S = 0.0;
-    return cw;
+  S = SPIN ? f.cspin * (T / n) * B : 0.0;
+  return wval<SPIN, PREC>(phi, S);
+}
+
+// The three levels of the discretisation estimate (Sec. 4.1) from the sums
+// of the circle (points 0, 2, 4, ...; h = N/2 of them), square (1, 5, 9,
+// ...) and triangle (3, 7, 11, ...) sub-loops (q = N/4 points each).  The
+// N/2 level is the circle's w.  Paper mode combines the sub-loop phases
+// (and spin exponents) as c/2 + s/4 + t/4 for the N level and (s + t)/2 for
+// the N/4 level; full mode averages the square and triangle w for the N/4
+// level and leaves the N level to the caller (the whole loop).
+template <bool SPIN, int PREC>
+__device__ __forceinline__ void disc_levels(double Ac, double Bc, double As, double Bs,
+                                            double At, double Bt, double T, int32_t h,
+                                            int32_t q, const FieldArgs& f, bool full,
+                                            double& w1, double& w2, double& w4) {
+  const double pc = f.cphi * Ac, ps = f.cphi * As, pt = f.cphi * At;
+  double sc = 0.0, ss = 0.0, st = 0.0;
+  if constexpr (SPIN) {
+    sc = f.cspin * (T / h) * Bc;
+    ss = f.cspin * (T / q) * Bs;
+    st = f.cspin * (T / q) * Bt;
+  }
+  w2 = wval<SPIN, PREC>(pc, sc);
+  if (full) {
+    w4 = 0.5 * (wval<SPIN, PREC>(ps, ss) + wval<SPIN, PREC>(pt, st));
   } else {
-    S = f.cspin * (T / n) * B;
-    if constexpr (PREC == 2) {
-      const double e = exp(fabs(S));
-      return cw * 0.5 * (e + 1.0 / e);
-    } else {
-      const double t = fabs(S) * 1.4426950408889634074;  // |S| log2(e)
-      const double k = floor(t);
-      const float p = __builtin_amdgcn_exp2f((float)(t - k));  // 2^frac in [1,2)
-      const int ki = (int)fminf((float)k, 2000.0f);
-      return cw * 0.5 * (ldexp((double)p, ki) + ldexp(1.0 / (double)p, -ki));
-    }
+    w1 = wval<SPIN, PREC>(0.5 * pc + 0.25 * ps + 0.25 * pt, 0.5 * sc + 0.25 * ss + 0.25 * st);
+    w4 = wval<SPIN, PREC>(0.5 * (ps + pt), 0.5 * (ss + st));
   }
 }
 
@@ -368,7 +406,7 @@ __device__ __forceinline__ void run_item(
   for (int64_t l = l0; l < l1; ++l) {
     double A, B, phi, S;
     if constexpr (PREC == 2) {
-      loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+      loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
     } else {
       loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
     }
@@ -420,7 +458,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
     if (l < l1) {
       double A, B, phi, S;
       if constexpr (PREC == 2) {
-        loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+        loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
       } else {
         loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
       }
@@ -429,6 +467,86 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
     __syncthreads();
   }
   if (valid) out[gs * n_pts + p] = acc;
+}
+
+// Discretisation estimate (Sec. 4.1): the schedule, workgroup shape and
+// barrier of k_average, with the loop split into its circle, square and
+// triangle sub-loops (for FP32 from the sub-loop segment array `sub`, for
+// FP64 from the raw coordinates at stride 2 and 4) and three accumulators,
+// one per level (N, N/2, N/4).  With `full`, the N level is the whole loop
+// (segment array `seg`), which doubles the segment work.  Output level k of
+// item gs lands in out[(k * G * n_sub + gs) * n_pts + p].
+template <int KIND, bool SPIN, int PREC>
+__global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
+    const float4* __restrict__ seg, const float4* __restrict__ sub,
+    const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
+    const double* __restrict__ rho_g, const double* __restrict__ T_g,
+    int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc, int32_t full,
+    double* __restrict__ out) {
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t lane = threadIdx.x % kWave;
+  const int64_t item = remap_wg(blockIdx.x, sc.n_wg, sc.n_xcd) * avg_waves(PREC) + wave;
+  const bool live = item < sc.n_items;
+  const int64_t it = live ? item : 0;
+  const int32_t chunk = (int32_t)(it % sc.n_chunks);
+  const int64_t gs = it / sc.n_chunks;  // g * n_sub + sub
+  const int64_t g = gs / sc.n_sub;
+  const int64_t sr = gs % sc.n_sub;
+  const int64_t l0 = g * sc.loops_per_group + sr * sc.loops_per_sub;
+  int64_t l1 = l0 + sc.loops_per_sub;
+  const int64_t gend = (g + 1) * sc.loops_per_group;
+  if (l1 > gend) l1 = gend;
+  if (!live) l1 = l0;
+
+  const int32_t p = chunk * kWave + lane;
+  const bool valid = live && p < n_pts;
+  const int32_t pp = p < n_pts ? p : n_pts - 1;
+  const double rho = rho_g[pp / n_T];
+  const double T = T_g[pp % n_T];
+  const double s = sqrt(T);
+  const LaneF32 c = lane_consts(rho, s, T);
+  const int32_t h = n_ppl / 2, q = n_ppl / 4;
+
+  double acc1 = 0.0, acc2 = 0.0, acc4 = 0.0;
+  for (int64_t k = 0; k < sc.loops_per_sub; ++k) {
+    const int64_t l = l0 + k;
+    if (l < l1) {
+      double Ac, Bc, As, Bs, At, Bt;
+      if constexpr (PREC == 2) {
+        const float* x = X + l * n_ppl;
+        const float* y = Y + l * n_ppl;
+        loop_sums_f64<KIND, SPIN>(x, y, 2, h, rho, s, f, Ac, Bc);
+        loop_sums_f64<KIND, SPIN>(x + 1, y + 1, 4, q, rho, s, f, As, Bs);
+        loop_sums_f64<KIND, SPIN>(x + 3, y + 3, 4, q, rho, s, f, At, Bt);
+      } else {
+        const float4* u = sub + l * n_ppl;
+        loop_sums_f32<KIND, SPIN, PREC == 0>(u, h, c, f, Ac, Bc);
+        loop_sums_f32<KIND, SPIN, PREC == 0>(u + h, q, c, f, As, Bs);
+        loop_sums_f32<KIND, SPIN, PREC == 0>(u + h + q, q, c, f, At, Bt);
+      }
+      double w1 = 0.0, w2, w4;
+      disc_levels<SPIN, PREC>(Ac, Bc, As, Bs, At, Bt, T, h, q, f, full != 0, w1, w2, w4);
+      if (full) {
+        double A, B, phi, S;
+        if constexpr (PREC == 2) {
+          loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
+        } else {
+          loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
+        }
+        w1 = epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
+      }
+      acc1 += w1;
+      acc2 += w2;
+      acc4 += w4;
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    const int64_t L = sc.n_items / sc.n_chunks;  // G * n_sub
+    out[gs * n_pts + p] = acc1;
+    out[(L + gs) * n_pts + p] = acc2;
+    out[(2 * L + gs) * n_pts + p] = acc4;
+  }
 }
 
 // Batched evaluation of uneven requests in one persistent launch.  Items of
@@ -548,10 +666,13 @@ __global__ __launch_bounds__(256) void k_stats_batch(const BatchHeader* __restri
 
 __global__ void k_zero_u32(unsigned int* __restrict__ p) { *p = 0u; }
 
+// Per-loop values of the (sub-)loop that takes, within each loop of the
+// ensemble, segments seg_off .. seg_off+m-1 of `seg` (FP32 paths) or the m
+// points x_off + k*x_stride of the raw coordinates (FP64 path).
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
     const float4* __restrict__ seg, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl,
+    const float* __restrict__ Y, int32_t n_ppl, SubLoop sl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, int32_t n_chunks, FieldArgs f, int64_t loop0,
     int64_t n_loops, double* __restrict__ o_phase, double* __restrict__ o_spin,
@@ -572,11 +693,12 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   const LaneF32 c = lane_consts(rho, s, T);
   double A, B, phi, S;
   if constexpr (PREC == 2) {
-    loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, rho, s, f, A, B);
+    loop_sums_f64<KIND, SPIN>(X + l * n_ppl + sl.x_off, Y + l * n_ppl + sl.x_off, sl.x_stride,
+                              sl.m, rho, s, f, A, B);
   } else {
-    loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
+    loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl + sl.seg_off, sl.m, c, f, A, B);
   }
-  const double w = epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
+  const double w = epilogue<SPIN, PREC>(A, B, T, sl.m, f, phi, S);
   if (valid) {
     const int64_t o = li * n_pts + p;
     o_phase[o] = phi;
@@ -585,8 +707,20 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   }
 }
 
-// Per-segment unit quantities (see wl_internal.h), formed in FP64 from the
-// FP32 coordinates and rounded once to FP32; flags non-finite input.
+// Per-segment unit quantities (see wl_internal.h) of the segment from
+// (x0, y0) to (x1, y1), formed in FP64 and rounded once to FP32.
+__device__ __forceinline__ float4 seg_quantities(float x0f, float y0f, float x1f, float y1f) {
+  const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
+  float4 o;
+  o.x = (float)(0.5 * (x0 + x1));
+  o.y = (float)(0.5 * (y0 + y1));
+  o.z = (float)(y1 - y0);
+  o.w = (float)(x0 * y1 - y0 * x1);
+  return o;
+}
+
+// Segment array of every loop (segment i: point i -> i+1 mod N); flags
+// non-finite input.
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
                                               const float* __restrict__ Y,
                                               int64_t n_loops, int32_t n_ppl,
@@ -601,14 +735,40 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
     const float x0f = X[l * n_ppl + i], y0f = Y[l * n_ppl + i];
     const float x1f = X[l * n_ppl + j], y1f = Y[l * n_ppl + j];
     if (!isfinite(x0f) || !isfinite(y0f)) *bad = 1;
-    const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
-    const double mx = 0.5 * (x0 + x1), my = 0.5 * (y0 + y1);
-    float4 o;
-    o.x = (float)mx;
-    o.y = (float)my;
-    o.z = (float)(y1 - y0);
-    o.w = (float)(x0 * y1 - y0 * x1);
-    seg[t] = o;
+    seg[t] = seg_quantities(x0f, y0f, x1f, y1f);
+  }
+}
+
+// Sub-loop segment array of every loop (N divisible by 4), N entries per
+// loop: [0, N/2) the circle sub-loop (point 2j -> 2j+2), [N/2, 3N/4) the
+// square one (4j+1 -> 4j+5), [3N/4, N) the triangle one (4j+3 -> 4j+7),
+// point indices mod N.
+__global__ __launch_bounds__(256) void k_prep_sub(const float* __restrict__ X,
+                                                  const float* __restrict__ Y,
+                                                  int64_t n_loops, int32_t n_ppl,
+                                                  float4* __restrict__ sub) {
+  const int64_t total = n_loops * n_ppl;
+  const int32_t h = n_ppl / 2, q = n_ppl / 4;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = t / n_ppl;
+    const int32_t i = (int32_t)(t % n_ppl);
+    int32_t a, step;
+    if (i < h) {
+      a = 2 * i;
+      step = 2;
+    } else if (i < h + q) {
+      a = 4 * (i - h) + 1;
+      step = 4;
+    } else {
+      a = 4 * (i - h - q) + 3;
+      step = 4;
+    }
+    int32_t b = a + step;
+    if (b >= n_ppl) b -= n_ppl;
+    const float* x = X + l * n_ppl;
+    const float* y = Y + l * n_ppl;
+    sub[t] = seg_quantities(x[a], y[a], x[b], y[b]);
   }
 }
 
@@ -638,6 +798,35 @@ __global__ __launch_bounds__(256) void k_stats(const double* __restrict__ sums,
   if (err) err[p] = e;
 }
 
+// Discretisation estimate, per grid point: the extrapolated level's group
+// sums (8/3 W_N - 2 W_N/2 + 1/3 W_N/4, group by group, written as level 3),
+// then mean and group standard error of the four levels and
+// delta = |W_N - W_inf| (Sec. 4.1).  sums: [4][G][n_pts].
+__global__ __launch_bounds__(256) void k_disc_finish(double* __restrict__ sums,
+                                                     int32_t n_groups, int32_t n_pts,
+                                                     int64_t n_loops,
+                                                     double* __restrict__ mean,
+                                                     double* __restrict__ err,
+                                                     double* __restrict__ delta) {
+  const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pts) return;
+  const int64_t L = (int64_t)n_groups * n_pts;
+  for (int32_t g = 0; g < n_groups; ++g) {
+    const int64_t o = (int64_t)g * n_pts + p;
+    sums[3 * L + o] = (8.0 * sums[o] - 6.0 * sums[L + o] + sums[2 * L + o]) / 3.0;
+  }
+  double m0 = 0.0, m3 = 0.0;
+  for (int32_t k = 0; k < 4; ++k) {
+    double m, e;
+    stats_point(sums + k * L, n_groups, n_pts, n_loops, p, m, e);
+    if (mean) mean[(int64_t)k * n_pts + p] = m;
+    if (err) err[(int64_t)k * n_pts + p] = e;
+    if (k == 0) m0 = m;
+    if (k == 3) m3 = m;
+  }
+  if (delta) delta[p] = fabs(m0 - m3);
+}
+
 // ------------------------------------------------------------ dispatch
 template <int KIND, bool SPIN, int PREC>
 hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const float* X,
@@ -653,8 +842,21 @@ hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const float* X,
 }
 
 template <int KIND, bool SPIN, int PREC>
+hipError_t launch_disc_t(const FieldArgs& f, const float4* seg, const float4* sub,
+                         const float* X, const float* Y, int32_t n_ppl, const double* rho,
+                         const double* T, int32_t n_T, int32_t n_pts, const Sched& s0,
+                         int32_t full, double* out, hipStream_t st) {
+  Sched s = s0;
+  s.n_wg = (int32_t)((s.n_items + avg_waves(PREC) - 1) / avg_waves(PREC));
+  hipLaunchKernelGGL((k_disc<KIND, SPIN, PREC>), dim3(s.n_wg),
+                     dim3(avg_waves(PREC) * kWave), 0, st, seg, sub, X, Y, n_ppl, rho, T,
+                     n_T, n_pts, f, s, full, out);
+  return hipGetLastError();
+}
+
+template <int KIND, bool SPIN, int PREC>
 hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const float* X,
-                       const float* Y, int32_t n_ppl, const double* rho,
+                       const float* Y, int32_t n_ppl, const SubLoop& sl, const double* rho,
                        const double* T, int32_t n_T, int32_t n_pts,
                        int64_t loop0, int64_t n_loops, double* ph, double* sp,
                        double* w, hipStream_t st) {
@@ -662,7 +864,7 @@ hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const float* X,
   const int64_t items = n_loops * n_chunks;
   const int64_t n_wg = (items + kWavesPerWG - 1) / kWavesPerWG;
   hipLaunchKernelGGL((k_per_loop<KIND, SPIN, PREC>), dim3((uint32_t)n_wg),
-                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
+                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, sl, rho, T,
                      n_T, n_pts, n_chunks, f, loop0, n_loops, ph, sp, w);
   return hipGetLastError();
 }
@@ -720,13 +922,40 @@ hipError_t launch_average(int precision, int spin, const FieldArgs& f,
 
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            const float4* d_seg, const float* d_x,
-                           const float* d_y, int32_t n_ppl,
+                           const float* d_y, int32_t n_ppl, const SubLoop& sl,
                            const double* d_rho, const double* d_T, int32_t n_T,
                            int32_t n_pts, int64_t loop0, int64_t n_loops,
                            double* d_phase, double* d_spin, double* d_w,
                            hipStream_t stream) {
-  WL_DISPATCH(launch_pl_t, f, d_seg, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
+  WL_DISPATCH(launch_pl_t, f, d_seg, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
               loop0, n_loops, d_phase, d_spin, d_w, stream)
+}
+
+hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
+                           int32_t n_ppl, float4* d_sub, hipStream_t stream) {
+  const int64_t total = n_loops * n_ppl;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_prep_sub, dim3((uint32_t)blocks), dim3(256), 0, stream, d_x, d_y,
+                     n_loops, n_ppl, d_sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
+                       const float4* d_sub, const float* d_x, const float* d_y,
+                       int32_t n_ppl, const double* d_rho, const double* d_T, int32_t n_T,
+                       int32_t n_pts, const Sched& s, int32_t full, double* d_out,
+                       hipStream_t stream) {
+  WL_DISPATCH(launch_disc_t, f, d_seg, d_sub, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts, s,
+              full, d_out, stream)
+}
+
+hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
+                              int64_t n_loops, double* d_mean, double* d_err,
+                              double* d_delta, hipStream_t stream) {
+  hipLaunchKernelGGL(k_disc_finish, dim3((uint32_t)((n_pts + 255) / 256)), dim3(256), 0,
+                     stream, d_sums, n_groups, n_pts, n_loops, d_mean, d_err, d_delta);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,

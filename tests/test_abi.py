@@ -66,6 +66,13 @@ def test_null_arguments_are_rejected_without_a_device(wl):
         # a NULL context is rejected before anything else is read
         assert f(None, None, None, None, 0, None, 0, 0, 0, None, None, None) \
             == wl.WL_EINVAL
+    lib.wl_discretisation.restype = ctypes.c_int
+    assert lib.wl_discretisation(None, None, None, None, 0, None, 0, 0, 0, 0, None, None,
+                                 None, None) == wl.WL_EINVAL
+    lib.wl_subloop_per_loop.restype = ctypes.c_int
+    assert lib.wl_subloop_per_loop(None, None, None, None, 0, None, 0, 0, 0, 0,
+                                   ctypes.c_int64(0), ctypes.c_int64(0), None, None,
+                                   None) == wl.WL_EINVAL
     lib.wl_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     assert lib.wl_set_timing(None, 1) == wl.WL_EINVAL
     lib.wl_last_kernel_ms.argtypes = [ctypes.c_void_p, ctypes.c_void_p]

@@ -1,0 +1,279 @@
+"""Discretisation estimate (Sec. 4.1) on the GPU vs the FP64 oracle, through
+the C ABI (wl_discretisation, wl_subloop_per_loop).
+
+Tolerances: per sub-loop, the per-loop bounds of the main path (a sub-loop
+is a loop of M points).  For the levels, each loop's w is a combination of
+sub-loop terms whose sizes are bounded by cosh(S) for the largest spin
+exponent S among them, so the level sums and means are compared on the
+envelope scale E = (1/N_l) sum_l cosh(S_l) max(1, S_l) (1 for scalar loops)
+with the main path's mean tolerance; the extrapolated level and delta carry
+the weights 8/3 + 2 + 1/3 = 5 of the combination.  Expected values come only
+from the oracle or, for the constant field, from exact Gaussian averages."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import wlinputs
+from disc_exact import exact_levels
+from wl_tol import TOL, check_per_loop, phase_limit
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = {
+    "const": (0, 0.9, 1.0),
+    "sech2": (1, 1.3, 0.7),
+    "gauss": (2, 2.0, 0.9),
+    "rational": (3, 1.5, 0.8),
+}
+PRECS = {"fp32c": 0, "fp32": 1, "fp64": 2}
+RHO = np.array([0.0, 0.3, 1.1, 2.5, 5.0])
+TGRID = np.geomspace(1e-3, 30.0, 13)  # 65 grid points: one full chunk + 1
+NL, NPPL, G = 128, 204, 4  # N/2 = 102 and N/4 = 51 segments: blocks of 8 plus tails
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wl():
+    import paper_1407_7486_amd as wl
+    return wl
+
+
+@pytest.fixture(scope="module")
+def ctx(wl):
+    c = wl.wl_create(0, None)
+    yield c
+    wl.wl_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def small(wl, ctx):
+    x, y = wlinputs.polygon_loops(NL, NPPL, seed=23)
+    ens = wl.wl_ensemble_upload(ctx, x, y, G)
+    yield x, y, ens
+    wl.wl_ensemble_free(ens)
+
+
+_CACHE = {}
+
+
+def sub_oracle(x, y, kind, eB0, lam, spin):
+    """Per-loop oracle values of the three sub-loops and of the whole loop."""
+    key = (id(x), kind, eB0, lam, spin)
+    if key not in _CACHE:
+        subs = [oracle.evaluate(sx, sy, kind, eB0, lam, RHO, TGRID, spin, 1, per_loop=True)
+                for sx, sy in oracle.subloops(x, y)]
+        full = oracle.evaluate(x, y, kind, eB0, lam, RHO, TGRID, spin, 1, per_loop=True)
+        _CACHE[key] = subs, full
+    return _CACHE[key]
+
+
+def envelope(subs, full, spin, n_groups):
+    """Per-loop envelope cosh(S) max(1, S) over all terms (sub-loops and the
+    whole loop); returns (its mean over loops, its per-group sums)."""
+    if spin:
+        s = np.max(np.abs(np.stack([o["spin"] for o in subs] + [full["spin"]])), axis=0)
+        e = np.cosh(s) * np.maximum(1.0, s)
+    else:
+        e = np.ones_like(full["w"])
+    nl = e.shape[0]
+    return e.mean(axis=0), e.reshape(n_groups, nl // n_groups, *e.shape[1:]).sum(axis=1)
+
+
+def check_levels(prec, mean, err, delta, sums, o, env_mean, env_group, n_loops):
+    tol = TOL[prec]["mean"]
+    for k in range(4):
+        c = 5.0 if k == 3 else 1.0
+        dm = np.abs(mean[k] - o["mean"][k])
+        lim = c * tol * env_mean
+        assert (dm <= lim).all(), f"level {k} mean: worst {(dm / lim).max():.3g}x"
+        ds = np.abs(sums[k] - o["group_sums"][k])
+        lims = c * tol * env_group
+        assert (ds <= lims).all(), f"level {k} group sums: worst {(ds / lims).max():.3g}x"
+    dd = np.abs(delta - o["delta"])
+    assert (dd <= 6.0 * tol * env_mean).all()
+    # error and delta follow from the returned group sums
+    for k in range(4):
+        _, e2, _ = oracle.stats(sums[k], n_loops)
+        np.testing.assert_allclose(err[k], e2, rtol=1e-9, atol=1e-300)
+    np.testing.assert_allclose(delta, np.abs(mean[0] - mean[3]), rtol=0, atol=0)
+    np.testing.assert_allclose(sums[3], (8 * sums[0] - 6 * sums[1] + sums[2]) / 3,
+                               rtol=1e-12, atol=1e-12 * np.abs(sums[:3]).max())
+
+
+@pytest.mark.parametrize("fname", list(FIELDS))
+@pytest.mark.parametrize("spin", [0, 1])
+@pytest.mark.parametrize("pname", list(PRECS))
+def test_subloop_per_loop(wl, ctx, small, fname, spin, pname):
+    kind, eB0, lam = FIELDS[fname]
+    prec = PRECS[pname]
+    x, y, ens = small
+    say("sub-loop per loop", fname, "spin", spin, pname)
+    subs, _ = sub_oracle(x, y, kind, eB0, lam, spin)
+    fld = wl.field(kind, eB0, lam)
+    for which, o in enumerate(subs):
+        m = NPPL // 2 if which == 0 else NPPL // 4
+        ph, sp, w = wl.wl_subloop_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, which, 0, NL)
+        check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin,
+                       o["phase_abs"], m)
+
+
+@pytest.mark.parametrize("fname", list(FIELDS))
+@pytest.mark.parametrize("spin", [0, 1])
+@pytest.mark.parametrize("pname", list(PRECS))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_levels_small(wl, ctx, small, fname, spin, pname, mode):
+    """Group sums split over loop sub-ranges (4 groups of 32 loops)."""
+    kind, eB0, lam = FIELDS[fname]
+    prec = PRECS[pname]
+    x, y, ens = small
+    say("levels", fname, "spin", spin, pname, "mode", mode)
+    subs, full = sub_oracle(x, y, kind, eB0, lam, spin)
+    o = oracle.discretisation(x, y, kind, eB0, lam, RHO, TGRID, spin, G, mode=mode)
+    fld = wl.field(kind, eB0, lam)
+    mean, err, delta, sums = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, spin, prec, mode)
+    check_levels(prec, mean, err, delta, sums, o, *envelope(subs, full, spin, G), NL)
+
+
+@pytest.mark.parametrize("spin", [0, 1])
+@pytest.mark.parametrize("pname", ["fp32c", "fp64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_levels_per_loop(wl, ctx, small, spin, pname, mode):
+    """One loop per group: the group sums are each loop's level values,
+    checked loop by loop against the oracle with the per-loop phase bounds
+    of the terms (no sub-range split on this path)."""
+    prec = PRECS[pname]
+    kind, eB0, lam = FIELDS["sech2"]
+    x, y, _ = small
+    say("levels per loop", "spin", spin, pname, "mode", mode)
+    ens = wl.wl_ensemble_upload(ctx, x, y, NL)
+    try:
+        fld = wl.field(kind, eB0, lam)
+        _, _, _, sums = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, spin, prec, mode)
+    finally:
+        wl.wl_ensemble_free(ens)
+    subs, full = sub_oracle(x, y, kind, eB0, lam, spin)
+    o = oracle.discretisation(x, y, kind, eB0, lam, RHO, TGRID, spin, G, mode=mode,
+                              per_loop=True)
+    terms = subs + [full]
+    ms = [NPPL // 2, NPPL // 4, NPPL // 4, NPPL]
+    lim_ph = np.max(np.stack([phase_limit(prec, t["phase"], t["phase_abs"], m)
+                              for t, m in zip(terms, ms)]), axis=0)
+    if spin:
+        s = np.max(np.abs(np.stack([t["spin"] for t in terms])), axis=0)
+        lim = (lim_ph + TOL[prec]["spin"] * np.maximum(1.0, s)) * np.cosh(s) * 1.01
+    else:
+        lim = lim_ph * 1.01
+    for k in range(3):
+        d = np.abs(sums[k] - o["w"][k])
+        assert (d <= lim).all(), f"level {k}: worst {(d / lim).max():.3g}x"
+
+
+def test_constant_field_levels_are_exact(wl, ctx):
+    """2^16 d-loops of 64 points in a constant field: every level against
+    its exact Gaussian average (both modes, FP32C and FP64), within 4.5
+    group standard errors; spinor levels are the scalar ones times
+    cosh(eB T)."""
+    say("constant field exact levels, 65536 x 64")
+    nl, n = 1 << 16, 64
+    x, y = wlinputs.dloop_ensemble(nl, n, seed=31)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 64)
+    try:
+        T = np.array([0.5, 1.0, 2.0, 4.0])
+        rho = np.array([0.0, 3.0])
+        fld = wl.field(0, 1.0, 1.0)
+        for mode in (0, 1):
+            want = np.array([exact_levels(n, th, mode) for th in T]).T  # (3, n_T)
+            for prec in (0, 2):
+                mean, err, _, _ = wl.wl_discretisation(ctx, ens, fld, rho, T, 0, prec, mode)
+                for j in range(rho.size):
+                    d = np.abs(mean[:3, j] - want)
+                    assert (d < 4.5 * err[:3, j]).all(), (mode, prec, d / err[:3, j])
+                ms, _, _, _ = wl.wl_discretisation(ctx, ens, fld, rho, T, 1, prec, mode)
+                np.testing.assert_allclose(ms[:3], mean[:3] * np.cosh(T), rtol=1e-6)
+    finally:
+        wl.wl_ensemble_free(ens)
+
+
+def test_full_size_sampled(wl, ctx):
+    """The sech^2 spinor workload at full size (65536 loops x 4096 points,
+    64 x 64 grid, 64 groups) in both modes: the level group sums of groups
+    0 and 63 at four grid points against the oracle on those groups'
+    loops."""
+    wk = wlinputs.WORKLOADS["sech2_spinor_64k"]
+    nl, n, G64 = wk["n_loops"], wk["n_ppl"], wk["n_groups"]
+    say("full size disc", nl, "x", n)
+    x, y = wlinputs.dloop_ensemble(nl, n, seed=0)
+    rho = wlinputs.rho_grid(*wk["rho"])
+    T = wlinputs.t_grid(*wk["T"])
+    kind, eB0, lam, spin = wk["kind"], wk["eB0"], wk["lam"], wk["spin"]
+    ens = wl.wl_ensemble_upload(ctx, x, y, G64)
+    try:
+        fld = wl.field(kind, eB0, lam)
+        res = {m: wl.wl_discretisation(ctx, ens, fld, rho, T, spin, 0, m) for m in (0, 1)}
+    finally:
+        wl.wl_ensemble_free(ens)
+    lpg = nl // G64
+    jj, tt = np.array([0, 9, 40, 63]), np.array([0, 30, 50, 63])
+    for g in (0, G64 - 1):
+        xs, ys = x[g * lpg:(g + 1) * lpg], y[g * lpg:(g + 1) * lpg]
+        for j, t in zip(jj, tt):
+            say("group", g, "rho", rho[j], "T", T[t])
+            subs = [oracle.evaluate(sx, sy, kind, eB0, lam, rho[j:j + 1], T[t:t + 1], spin, 1,
+                                    per_loop=True) for sx, sy in oracle.subloops(xs, ys)]
+            full = oracle.evaluate(xs, ys, kind, eB0, lam, rho[j:j + 1], T[t:t + 1], spin, 1,
+                                   per_loop=True)
+            s = np.max(np.abs(np.stack([o["spin"] for o in subs] + [full["spin"]])), axis=0)
+            env = float((np.cosh(s) * np.maximum(1.0, s)).sum())
+            for m in (0, 1):
+                o = oracle.discretisation(xs, ys, kind, eB0, lam, rho[j:j + 1], T[t:t + 1],
+                                          spin, 1, mode=m)
+                sums = res[m][3]
+                for k in range(4):
+                    c = 5.0 if k == 3 else 1.0
+                    d = abs(sums[k, g, j, t] - o["group_sums"][k, 0, 0, 0])
+                    assert d <= c * TOL[0]["mean"] * env, (g, j, t, m, k, d / env)
+
+
+def test_deterministic_and_invalid(wl, ctx, small):
+    x, y, ens = small
+    say("disc determinism and invalid arguments")
+    fld = wl.field(1, 1.3, 0.7)
+    a = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, 1, 0, 0)
+    b = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, 1, 0, 0)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v, equal_nan=True)
+    with pytest.raises(wl.WLError) as ei:
+        wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, 1, 0, 2)
+    assert ei.value.code == wl.WL_EINVAL
+    with pytest.raises(wl.WLError) as ei:
+        wl.wl_subloop_per_loop(ctx, ens, fld, RHO, TGRID, 1, 0, 3, 0, 4)
+    assert ei.value.code == wl.WL_EINVAL
+    # loops whose point count is not a multiple of 4 have no sub-loops
+    x6, y6 = wlinputs.polygon_loops(8, 18, seed=2)
+    e6 = wl.wl_ensemble_upload(ctx, x6, y6, 2)
+    try:
+        with pytest.raises(wl.WLError) as ei:
+            wl.wl_discretisation(ctx, e6, fld, RHO, TGRID, 1, 0, 0)
+        assert ei.value.code == wl.WL_EINVAL
+        with pytest.raises(wl.WLError):
+            wl.wl_subloop_per_loop(ctx, e6, fld, RHO, TGRID, 1, 2, 0, 0, 8)
+    finally:
+        wl.wl_ensemble_free(e6)
+    # empty grid: nothing to do
+    m, e, d, s = wl.wl_discretisation(ctx, ens, fld, np.zeros(0), TGRID, 1, 0, 0)
+    assert m.size == 0
+    # 8-point loops: the square and triangle sub-loops have 2 points (no area)
+    x8, y8 = wlinputs.polygon_loops(8, 8, seed=4)
+    e8 = wl.wl_ensemble_upload(ctx, x8, y8, 2)
+    try:
+        o = oracle.discretisation(x8, y8, 1, 1.3, 0.7, RHO, TGRID, 1, 2, mode=1)
+        mean, _, _, sums = wl.wl_discretisation(ctx, e8, fld, RHO, TGRID, 1, 2, 1)
+        np.testing.assert_allclose(sums, o["group_sums"], rtol=1e-11, atol=1e-11)
+    finally:
+        wl.wl_ensemble_free(e8)

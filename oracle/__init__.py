@@ -17,6 +17,11 @@ Contents
                          interleaved sub-loops, three levels of <W>, the
                          parabolic extrapolation to N = infinity and its
                          distance from the N-point level.
+  * ``action``        -- effective action density and action per group from
+                         the group sums (Sec. 3.3 small-T series below a,
+                         Simpson in x = 1/(1 + T/T_max) above; the rho_cm
+                         integral of Eq. cylEA), with the locally-constant-
+                         field (LCF) comparison of Sec. 6.
   * ``vloop_ensemble``-- an independent loop generator (i.i.d. Gaussian
                          increments, closed by subtracting their mean) that
                          samples the same discrete law as the d-loops of
@@ -281,6 +286,120 @@ def discretisation(x, y, kind, eB0, lam, rho, T, spin, n_groups,
     if per_loop:
         out.update(phase=np.stack(ph), spin=np.stack(sp), w=np.stack([w1, w2, w4]))
     return out
+
+
+# ------------------------------------------------------- effective action
+def small_t_coeffs(spin, b, m2):
+    """Coefficients c_1..c_4 of the small-T integrand sum_k c_k T^k for a
+    constant field b = eB (Sec. 3.3, Eqs. fermI for spinors and scalI for
+    scalars)."""
+    b = np.asarray(b, dtype=np.float64)
+    b4 = b ** 4
+    b6 = b ** 6
+    if spin:
+        return [-b4 / 45, b4 * m2 / 45, 2 * b6 / 945 - b4 * m2 * m2 / 90,
+                (7 * b4 * m2 ** 3 - 4 * b6 * m2) / 1890]
+    return [7 * b4 / 360, -7 * b4 * m2 / 360, (147 * b4 * m2 * m2 - 31 * b6) / 15120,
+            (31 * b6 * m2 - 49 * b4 * m2 ** 3) / 15120]
+
+
+def action_grids(a, T_max, n_T, rho_max, n_rho):
+    """Evaluation grids of the integrals of Sec. 6 (Implementation): the
+    half-line [a, inf) in T and [0, inf) in rho_cm are mapped to x in
+    (0, x_end] by x = 1/(1 + T/T_max) (x = 1/(1 + rho/rho_max)) and Simpson's
+    rule runs on n uniform intervals of x (n even); the node x = 0 (infinity)
+    needs no evaluation.  Returns (T[n_T], rho[n_rho]), both ascending:
+    T[0] = a, rho[0] = 0."""
+    if n_T < 2 or n_T % 2 or n_rho < 2 or n_rho % 2:
+        raise ValueError("Simpson needs an even number (>= 2) of intervals")
+    xa = 1.0 / (1.0 + a / T_max)
+    k = np.arange(n_T, 0, -1)
+    T = T_max * (1.0 / (k * xa / n_T) - 1.0)
+    T[0] = a
+    j = np.arange(n_rho, 0, -1)
+    rho = rho_max * (1.0 / (j / n_rho) - 1.0)
+    rho[0] = 0.0
+    return T, rho
+
+
+def _simpson_weights(n):
+    w = np.ones(n + 1)
+    w[1:-1:2] = 4.0
+    w[2:-1:2] = 2.0
+    return w / 3.0
+
+
+def action(group_sums, n_loops, kind, eB0, lam, spin, m2, a, T_max, rho_max):
+    """Effective action from the group sums on the grids of ``action_grids``
+    (group_sums shape (G, n_rho, n_T)).
+
+    Per group g, W_g = G S_g / N_l; the proper-time integrand (Eq. cylEA and
+    Sec. 3.3) is I = e^{-m^2 T}/T^3 [W_g - 1 - (eB T)^2/3] for spinors and
+    e^{-m^2 T}/T^3 [W_g - 1 + (eB T)^2/6] for scalars, eB = eB(rho_cm).  The
+    density D_g(rho) = int_0^inf I dT is the small-T series integrated from 0
+    to a plus Simpson's rule in x over [a, inf) (dT = T_max dx / x^2).  The
+    action per unit time and length is (1/4pi) int_0^inf rho D(rho) drho by
+    Simpson's rule in x (drho = rho_max dx / x^2); for the constant field it
+    diverges and is returned as NaN.  Errors are the standard error of the
+    group values (Sec. 4.2.3, integrals done group by group).  The LCF
+    comparison replaces W by the constant-field form at eB(rho_cm)
+    (theta coth theta, or theta / sinh theta for scalars, theta = eB T).
+
+    Returns a dict: ``T``, ``rho`` (the grids), ``density`` (G, n_rho),
+    ``density_mean``, ``density_err`` (n_rho), ``action`` (G),
+    ``action_mean``, ``action_err``, ``lcf_density`` (n_rho), ``lcf_action``.
+    """
+    S = np.asarray(group_sums, dtype=np.float64)
+    G, n_rho, n_T = S.shape
+    if m2 <= 0 or a <= 0 or T_max <= 0 or rho_max <= 0:
+        raise ValueError("m2, a, T_max and rho_max must be > 0")
+    T, rho = action_grids(a, T_max, n_T, rho_max, n_rho)
+    xa = 1.0 / (1.0 + a / T_max)
+    b = field_b(kind, eB0, lam, rho * rho)                       # (n_rho,)
+    th = b[:, None] * T[None, :]                                 # (n_rho, n_T)
+    counter = 1.0 + th * th / 3.0 if spin else 1.0 - th * th / 6.0
+    pre = np.exp(-m2 * T) / T ** 3
+    c = small_t_coeffs(spin, b, m2)
+    small = sum(c[k] * a ** (k + 2) / (k + 2) for k in range(4))  # int_0^a sum c_k T^k
+    # x nodes of the T integral, x_0 = 0 .. x_n = x_a; the grid is T[n-1] .. T[0]
+    x = np.arange(n_T + 1) * (xa / n_T)
+    wT = _simpson_weights(n_T) * (xa / n_T)
+    jac = np.zeros(n_T + 1)
+    jac[1:] = T_max / x[1:] ** 2
+    jac_T = jac[1:][::-1]                                        # per T grid point
+    wT_T = wT[1:][::-1]
+
+    def density(W):  # W: (..., n_rho, n_T)
+        integrand = pre * (W - counter)
+        return small + (integrand * (wT_T * jac_T)).sum(axis=-1)
+
+    xr = np.arange(n_rho + 1) / n_rho
+    wr = _simpson_weights(n_rho) / n_rho
+    jr = np.zeros(n_rho + 1)
+    jr[1:] = rho_max / xr[1:] ** 2
+    jr_rho = jr[1:][::-1]
+    wr_rho = wr[1:][::-1]
+
+    def rho_integral(D):
+        if kind == CONST:
+            return np.full(D.shape[:-1], np.nan)
+        return (rho * D * wr_rho * jr_rho).sum(axis=-1) / (4.0 * np.pi)
+
+    Wg = S * (G / n_loops)
+    D = density(Wg)
+    A = rho_integral(D)
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        Wl = np.where(th == 0, 1.0, th / np.tanh(th) if spin else th / np.sinh(th))
+    Dl = density(Wl)
+
+    def sem(v):
+        if G < 2:
+            return np.full(v.shape[1:], np.nan)
+        return np.sqrt(((v - v.mean(axis=0)) ** 2).sum(axis=0) / (G * (G - 1)))
+
+    return {"T": T, "rho": rho, "density": D, "density_mean": D.mean(axis=0),
+            "density_err": sem(D), "action": A, "action_mean": A.mean(axis=0),
+            "action_err": sem(A), "lcf_density": Dl, "lcf_action": rho_integral(Dl)}
 
 
 # ----------------------------------------------------------- closed forms

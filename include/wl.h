@@ -314,6 +314,60 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                         int32_t spin, int32_t precision, int32_t subloop, int64_t loop0,
                         int64_t n_loops, double* phase, double* spin_exp, double* w);
 
+/* ---- effective action (Eq. cylEA; Sec. 3.3, Renormalization; Sec. 6,
+ * Implementation) --------------------------------------------------------
+ * From the group sums of an evaluation on the grids of wl_action_grids, per
+ * group g with W_g = G S_g / N_l and eB = eB(rho_cm):
+ *   integrand  I(T) = e^{-m^2 T} / T^3 [W_g - 1 - (eB T)^2 / 3]   (spinor)
+ *              I(T) = e^{-m^2 T} / T^3 [W_g - 1 + (eB T)^2 / 6]   (scalar)
+ *   density    D_g(rho) = int_0^a (small-T series of I, Eqs. fermI and
+ *              scalI, to T^4) dT + int_a^inf I dT, the latter by Simpson's
+ *              rule on n_T uniform intervals of x = 1/(1 + T/T_max)
+ *   action     (1/4pi) int_0^inf rho D_g(rho) drho by Simpson's rule on
+ *              n_rho uniform intervals of x = 1/(1 + rho/rho_max) (per unit
+ *              time and length along the field; NaN for WL_CONST, whose
+ *              action diverges)
+ * and the mean and standard error over the groups (the integrals are done
+ * group by group, Sec. 4.2.3).  The LCF comparison (Sec. 6) is the same
+ * integral with W replaced by the constant-field form at eB(rho_cm):
+ * eB T coth(eB T) (spinor) or eB T / sinh(eB T) (scalar).  The scalar case
+ * uses the same measure (1/4pi) rho drho. */
+typedef struct wl_action_spec {
+  double m2;      /* mass squared, > 0 (units of eB)                        */
+  double a;       /* small-T cut: the series is used below a, > 0           */
+  double T_max;   /* scale of the T substitution, > 0                       */
+  double rho_max; /* scale of the rho substitution, > 0                     */
+  int32_t n_T;    /* Simpson intervals in T (even, >= 2) = T grid points    */
+  int32_t n_rho;  /* Simpson intervals in rho (even, >= 2) = rho grid points*/
+} wl_action_spec;
+
+/* Output pointers of wl_action; each may be NULL. */
+typedef struct wl_action_out {
+  double* density;      /* [G][n_rho] per group                             */
+  double* density_mean; /* [n_rho]                                          */
+  double* density_err;  /* [n_rho] standard error of the group densities    */
+  double* action;       /* [G]                                              */
+  double* action_mean;  /* [1]                                              */
+  double* action_err;   /* [1]                                              */
+  double* lcf_density;  /* [n_rho]                                         */
+  double* lcf_action;   /* [1]                                              */
+} wl_action_out;
+
+/* The grids the action integrals need: T[n_T] ascending with T[0] = a
+ * (x_k = k x_a / n_T, x_a = 1/(1 + a/T_max), k = n_T .. 1) and
+ * rho[n_rho] ascending with rho[0] = 0 (x_k = k / n_rho); the node x = 0
+ * (infinity) contributes nothing.  Host arrays.  Errors: WL_EINVAL. */
+int wl_action_grids(const wl_action_spec* spec, double* T, double* rho);
+
+/* Effective action from group sums [G][n_rho][n_T] evaluated on those grids
+ * (for example wl_average's, G = n_groups of an ensemble of n_loops loops)
+ * for the given field and spin.  flags WL_HOST_PTR: group_sums and the
+ * outputs are host memory; WL_DEVICE_PTR: device memory on the ctx device.
+ * Synchronous in both cases.  Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_action(wl_ctx* ctx, const wl_action_spec* spec, const wl_field* field,
+              int32_t spin, const double* group_sums, int32_t n_groups, int64_t n_loops,
+              int32_t flags, const wl_action_out* out);
+
 /* Kernel timing: when enabled, the main evaluation kernel of each
  * wl_average / wl_average_async / wl_discretisation call is bracketed by
  * HIP events on the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.

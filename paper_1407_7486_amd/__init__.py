@@ -34,7 +34,7 @@ EXPORTS = (
     "wl_last_kernel_ms", "wl_kernel_ms_total", "wl_average_batch",
     "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
-    "wl_discretisation", "wl_subloop_per_loop",
+    "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
 )
 
 
@@ -55,6 +55,18 @@ class wl_request(ctypes.Structure):
                 ("spin", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("err", ctypes.c_void_p),
                 ("group_sums", ctypes.c_void_p)]
+
+
+class wl_action_spec(ctypes.Structure):
+    _fields_ = [("m2", ctypes.c_double), ("a", ctypes.c_double), ("T_max", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("n_T", ctypes.c_int32),
+                ("n_rho", ctypes.c_int32)]
+
+
+class wl_action_out(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "density", "density_mean", "density_err", "action", "action_mean", "action_err",
+        "lcf_density", "lcf_action")]
 
 
 class wl_server_config(ctypes.Structure):
@@ -99,6 +111,9 @@ _sigs = {
                            _i32, _i32, _i32, _vp, _vp, _vp, _vp], ctypes.c_int),
     "wl_subloop_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
                              _i32, _i32, _i32, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "wl_action_grids": ([ctypes.POINTER(wl_action_spec), _vp, _vp], ctypes.c_int),
+    "wl_action": ([_vp, ctypes.POINTER(wl_action_spec), ctypes.POINTER(wl_field), _i32, _vp,
+                   _i32, _i64, _i32, ctypes.POINTER(wl_action_out)], ctypes.c_int),
     "wl_set_timing": ([_vp, _i32], ctypes.c_int),
     "wl_last_kernel_ms": ([_vp, ctypes.POINTER(_d)], ctypes.c_int),
     "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
@@ -245,6 +260,39 @@ def wl_subloop_per_loop(ctx, ens, fld, rho, T, spin, precision, subloop, loop0, 
                                     _ptr(T), T.size, int(spin), int(precision), int(subloop),
                                     int(loop0), int(n_loops), *[_ptr(a) for a in out]), ctx)
     return tuple(out)
+
+
+def action_spec(m2, a, T_max, n_T, rho_max, n_rho):
+    return wl_action_spec(float(m2), float(a), float(T_max), float(rho_max), int(n_T),
+                          int(n_rho))
+
+
+def wl_action_grids(spec):
+    """(T[n_T], rho[n_rho]) of the action integrals."""
+    T = np.zeros(spec.n_T)
+    rho = np.zeros(spec.n_rho)
+    rc = _lib.wl_action_grids(ctypes.byref(spec), _ptr(T), _ptr(rho))
+    if rc != WL_OK:
+        raise WLError(rc, "invalid action spec")
+    return T, rho
+
+
+def wl_action(ctx, spec, fld, spin, group_sums, n_loops):
+    """Effective action from host group sums (G, n_rho, n_T); returns a dict
+    of numpy arrays (density (G, n_rho), density_mean, density_err, action
+    (G,), action_mean, action_err, lcf_density, lcf_action)."""
+    S = _host_f64(group_sums)
+    G = S.shape[0]
+    nr = spec.n_rho
+    res = {"density": np.zeros((G, nr)), "density_mean": np.zeros(nr),
+           "density_err": np.zeros(nr), "action": np.zeros(G), "action_mean": np.zeros(1),
+           "action_err": np.zeros(1), "lcf_density": np.zeros(nr), "lcf_action": np.zeros(1)}
+    out = wl_action_out(*[_ptr(res[n]) for n, _ in wl_action_out._fields_])
+    _check(_lib.wl_action(ctx, ctypes.byref(spec), ctypes.byref(fld), int(spin), _ptr(S), G,
+                          int(n_loops), WL_HOST_PTR, ctypes.byref(out)), ctx)
+    for n in ("action_mean", "action_err", "lcf_action"):
+        res[n] = float(res[n][0])
+    return res
 
 
 def wl_average_async(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,

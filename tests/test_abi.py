@@ -73,6 +73,11 @@ def test_null_arguments_are_rejected_without_a_device(wl):
     assert lib.wl_subloop_per_loop(None, None, None, None, 0, None, 0, 0, 0, 0,
                                    ctypes.c_int64(0), ctypes.c_int64(0), None, None,
                                    None) == wl.WL_EINVAL
+    lib.wl_action.restype = ctypes.c_int
+    assert lib.wl_action(None, None, None, 0, None, 0, ctypes.c_int64(0), 0, None) \
+        == wl.WL_EINVAL
+    lib.wl_action_grids.restype = ctypes.c_int
+    assert lib.wl_action_grids(None, None, None) == wl.WL_EINVAL
     lib.wl_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     assert lib.wl_set_timing(None, 1) == wl.WL_EINVAL
     lib.wl_last_kernel_ms.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -102,3 +107,21 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE,
                          text=True).stdout
     assert "IMPORTERROR" in out and "not been built" in out
+
+
+def test_action_grids_match_the_oracle(wl):
+    """Host logic of the C ABI (no device): the action grids equal the
+    oracle's, and invalid specs are refused."""
+    import numpy as np
+
+    import oracle
+    for args in [(1.0, 0.05, 1.0, 32, 1.0, 16), (0.3, 0.01, 3.0, 64, 2.5, 40)]:
+        m2, a, Tm, nT, rm, nr = args
+        T, rho = wl.wl_action_grids(wl.action_spec(m2, a, Tm, nT, rm, nr))
+        To, ro = oracle.action_grids(a, Tm, nT, rm, nr)
+        np.testing.assert_allclose(T, To, rtol=1e-15)
+        np.testing.assert_allclose(rho, ro, rtol=1e-15)
+    for bad in [(1.0, 0.05, 1.0, 31, 1.0, 16), (1.0, 0.0, 1.0, 32, 1.0, 16),
+                (1.0, 0.05, 1.0, 32, 1.0, 0)]:
+        with pytest.raises(wl.WLError):
+            wl.wl_action_grids(wl.action_spec(*bad))

@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--workload", default="sech2_spinor_64k")
     ap.add_argument("--disc-steps", type=int, default=1,
                     help="timed calls of the discretisation estimate per mode (0: skip)")
+    ap.add_argument("--no-generate", action="store_true",
+                    help="skip timing the on-device loop generation")
     ap.add_argument("--cpu-loops", type=int, default=64,
                     help="loops in the oracle's timed CPU sample (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
@@ -195,7 +197,8 @@ def main():
     kname = KIND_NAMES[kind]
     t0 = time.time()
     x, y = wlinputs.dloop_ensemble(cfg["n_loops"], cfg["n_ppl"], seed=cfg["seed"])
-    log(f"[bench] generated {cfg['n_loops']}x{cfg['n_ppl']} d-loops in {time.time() - t0:.1f}s")
+    t_cpu_gen = time.time() - t0
+    log(f"[bench] generated {cfg['n_loops']}x{cfg['n_ppl']} d-loops in {t_cpu_gen:.1f}s")
     rho = wlinputs.rho_grid(*cfg["rho"])
     T = wlinputs.t_grid(*cfg["T"])
     G = cfg["n_groups"]
@@ -274,6 +277,24 @@ def main():
             log(f"[bench] disc {name}: kernel {kd / nd:.1f} ms, "
                 f"{evals / (kd * 1e-3):.4e} seg/s")
 
+    gen = None
+    if not args.no_generate:
+        # the same ensemble generated on the device (d-loops, same Philox stream)
+        wl.wl_set_timing(ctx, True)
+        t0 = time.perf_counter()
+        eg = wl.wl_ensemble_generate(ctx, cfg["seed"], 0, cfg["n_loops"], cfg["n_ppl"], G)
+        dtg = time.perf_counter() - t0
+        kg, _ = wl.wl_kernel_ms_total(ctx)
+        wl.wl_set_timing(ctx, False)
+        gx, gy = wl.wl_ensemble_download(eg, 0, 256)
+        wl.wl_ensemble_free(eg)
+        same = float(((gx == x[:256]).mean() + (gy == y[:256]).mean()) / 2)
+        npts = cfg["n_loops"] * cfg["n_ppl"]
+        gen = {"kernel_ms": kg, "points_per_s": npts / (kg * 1e-3), "call_s": dtg,
+               "cpu_generator_s": t_cpu_gen, "identical_fraction_first_256_loops": same}
+        log(f"[bench] device generation {kg:.1f} ms ({npts / (kg * 1e-3):.3e} points/s), "
+            f"CPU generator {t_cpu_gen:.1f} s, identical {same:.6f}")
+
     slots = SLOTS_FP32C[(kname, spin)]
     achieved = seg_per_step * slots / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
@@ -330,7 +351,7 @@ def main():
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
         "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "serve": serve,
-        "disc": disc,
+        "disc": disc, "generate": gen,
     }
     print(json.dumps(out), flush=True)
 

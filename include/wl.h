@@ -121,6 +121,28 @@ int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
                        int64_t n_loops, int32_t n_ppl, int32_t n_groups,
                        int32_t flags, wl_ens** out);
 
+/* Generate an ensemble on the device instead of uploading one: n_loops
+ * d-loops of n_ppl points (a power of two, 2 .. 8192; Sec. 2.1, Loop
+ * Generation, Eqs. yn2 and ynk), loops first_loop .. first_loop+n_loops-1
+ * of the stream keyed by `seed`.  Random numbers: Philox4x32-10 (Salmon et
+ * al., SC'11), key = seed, counter = (block, loop_lo, loop_hi, 0); uniforms
+ * (w + 0.5) 2^-32; Box-Muller pairs r = sqrt(-2 ln u1),
+ * (r cos 2 pi u2, r sin 2 pi u2); the new points of the recursion take the
+ * pairs in order (level by level, ascending), x from the cosine and y from
+ * the sine.  Each new point is the midpoint of its neighbours plus a normal
+ * of standard deviation 1/sqrt(N_k); the loop's mean is subtracted.  FP64
+ * arithmetic, stored as FP32.  The result is an ensemble like
+ * wl_ensemble_upload's.  Synchronous.
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_ensemble_generate(wl_ctx* ctx, uint64_t seed, int64_t first_loop, int64_t n_loops,
+                         int32_t n_ppl, int32_t n_groups, wl_ens** out);
+
+/* Copy loops loop0 .. loop0+n_loops-1 of an ensemble to host arrays
+ * [n_loops][n_ppl] (FP32; either pointer may be NULL).  Synchronous.
+ * Errors: WL_EINVAL, WL_EHIP. */
+int wl_ensemble_download(const wl_ens* ens, float* y_x, float* y_y, int64_t loop0,
+                         int64_t n_loops);
+
 /* Free an ensemble (NULL allowed).  Must be called before wl_destroy of the
  * context that created it. */
 int wl_ensemble_free(wl_ens* ens);
@@ -369,8 +391,9 @@ int wl_action(wl_ctx* ctx, const wl_action_spec* spec, const wl_field* field,
               int32_t flags, const wl_action_out* out);
 
 /* Kernel timing: when enabled, the main evaluation kernel of each
- * wl_average / wl_average_async / wl_discretisation call is bracketed by
- * HIP events on the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.
+ * wl_average / wl_average_async / wl_discretisation call, and the
+ * generation kernels of wl_ensemble_generate, are bracketed by HIP events on
+ * the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.
  * wl_last_kernel_ms waits for the last recorded launch and returns its
  * duration in milliseconds; wl_kernel_ms_total waits for all of them and
  * returns the sum of their durations and their count.  Both return

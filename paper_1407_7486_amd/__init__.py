@@ -35,6 +35,7 @@ EXPORTS = (
     "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
     "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
+    "wl_ensemble_generate", "wl_ensemble_download",
 )
 
 
@@ -99,6 +100,9 @@ _sigs = {
     "wl_ensemble_upload": ([_vp, _vp, _vp, _i64, _i32, _i32, _i32,
                             ctypes.POINTER(_vp)], ctypes.c_int),
     "wl_ensemble_free": ([_vp], ctypes.c_int),
+    "wl_ensemble_generate": ([_vp, ctypes.c_uint64, _i64, _i64, _i32, _i32,
+                              ctypes.POINTER(_vp)], ctypes.c_int),
+    "wl_ensemble_download": ([_vp, _vp, _vp, _i64, _i64], ctypes.c_int),
     "wl_ensemble_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
                           ctypes.POINTER(_i32)], ctypes.c_int),
     "wl_average": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
@@ -205,6 +209,25 @@ def wl_ensemble_upload(ctx, y_x, y_y, n_groups):
                                    WL_DEVICE_PTR if dev else WL_HOST_PTR,
                                    ctypes.byref(ens)), ctx)
     return ens
+
+
+def wl_ensemble_generate(ctx, seed, first_loop, n_loops, n_ppl, n_groups):
+    """d-loop ensemble generated on the device (see include/wl.h)."""
+    ens = _vp()
+    _check(_lib.wl_ensemble_generate(ctx, int(seed), int(first_loop), int(n_loops),
+                                     int(n_ppl), int(n_groups), ctypes.byref(ens)), ctx)
+    return ens
+
+
+def wl_ensemble_download(ens, loop0, n_loops):
+    """Loops loop0 .. loop0+n_loops-1 as FP32 numpy arrays (x, y)."""
+    _, n_ppl, _ = wl_ensemble_info(ens)
+    x = np.zeros((n_loops, n_ppl), dtype=np.float32)
+    y = np.zeros((n_loops, n_ppl), dtype=np.float32)
+    rc = _lib.wl_ensemble_download(ens, _ptr(x), _ptr(y), int(loop0), int(n_loops))
+    if rc != WL_OK:
+        raise WLError(rc, "wl_ensemble_download failed")
+    return x, y
 
 
 def wl_ensemble_free(ens):

@@ -238,6 +238,8 @@ using namespace wl;
 
 extern "C" {
 
+static hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b);
+
 const char* wl_version(void) { return "wl 0.1 (gfx950)"; }
 
 const char* wl_strerror(int code) {
@@ -355,6 +357,87 @@ int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
   if (err != hipSuccess) return cleanup(hip_fail(ctx, err, "ensemble upload"));
   if (bad) return cleanup(fail(ctx, WL_EINVAL, "non-finite loop coordinate"));
   *out = e;
+  return WL_OK;
+}
+
+int wl_ensemble_generate(wl_ctx* ctx, uint64_t seed, int64_t first_loop, int64_t n_loops,
+                         int32_t n_ppl, int32_t n_groups, wl_ens** out) {
+  if (!ctx) return WL_EINVAL;
+  ctx->err.clear();
+  if (!out) return fail(ctx, WL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_loops < 1) return fail(ctx, WL_EINVAL, "n_loops must be >= 1");
+  if (first_loop < 0) return fail(ctx, WL_EINVAL, "first_loop must be >= 0");
+  if (n_ppl < 2 || n_ppl > 8192 || (n_ppl & (n_ppl - 1)))
+    return fail(ctx, WL_EINVAL, "d-loops need n_ppl a power of two in [2, 8192]");
+  if (n_groups < 1 || n_loops % n_groups != 0)
+    return fail(ctx, WL_EINVAL, "n_groups must be >= 1 and divide n_loops");
+  if (n_loops > ((int64_t)1 << 40) / n_ppl) return fail(ctx, WL_EINVAL, "ensemble too large");
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const int64_t npts = n_loops * n_ppl;
+  wl_ens* e = new (std::nothrow) wl_ens();
+  if (!e) return fail(ctx, WL_ENOMEM, "host allocation failed");
+  e->ctx = ctx;
+  e->n_loops = n_loops;
+  e->n_ppl = n_ppl;
+  e->n_groups = n_groups;
+  auto cleanup = [&](int code) {
+    if (e->d_x) (void)hipFree(e->d_x);
+    if (e->d_y) (void)hipFree(e->d_y);
+    if (e->d_seg) (void)hipFree(e->d_seg);
+    delete e;
+    return code;
+  };
+  if (hipMalloc((void**)&e->d_x, npts * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&e->d_y, npts * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess) {
+    (void)hipGetLastError();
+    return cleanup(fail(ctx, WL_ENOMEM, "device allocation of %lld points failed",
+                        (long long)npts));
+  }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t err = hipSuccess;
+  if (ctx->timing) {
+    err = next_events(ctx, &ev0, &ev1);
+    if (err == hipSuccess) err = hipEventRecord(ev0, ctx->stream);
+  }
+  if (err == hipSuccess)
+    err = wl::launch_generate(seed, first_loop, n_loops, n_ppl, e->d_x, e->d_y, ctx->stream);
+  if (err == hipSuccess && ctx->timing) {
+    err = hipEventRecord(ev1, ctx->stream);
+    if (err == hipSuccess) ctx->n_timed++;
+  }
+  if (err == hipSuccess) err = hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream);
+  if (err == hipSuccess)
+    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, ctx->d_flag, ctx->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+  if (err != hipSuccess) return cleanup(hip_fail(ctx, err, "ensemble generation"));
+  *out = e;
+  return WL_OK;
+}
+
+int wl_ensemble_download(const wl_ens* ens, float* y_x, float* y_y, int64_t loop0,
+                         int64_t n_loops) {
+  if (!ens) return WL_EINVAL;
+  wl_ctx* ctx = ens->ctx;
+  ctx->err.clear();
+  if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
+    return fail(ctx, WL_EINVAL, "loop range [%lld, %lld) outside the ensemble",
+                (long long)loop0, (long long)(loop0 + n_loops));
+  if (n_loops == 0) return WL_OK;
+  DeviceGuard g(ctx->device);
+  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+  const size_t off = (size_t)(loop0 * ens->n_ppl), cnt = (size_t)(n_loops * ens->n_ppl);
+  hipError_t e = hipSuccess;
+  if (y_x)
+    e = hipMemcpyAsync(y_x, ens->d_x + off, cnt * sizeof(float), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess && y_y)
+    e = hipMemcpyAsync(y_y, ens->d_y + off, cnt * sizeof(float), hipMemcpyDeviceToHost,
+                       ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "wl_ensemble_download");
   return WL_OK;
 }
 

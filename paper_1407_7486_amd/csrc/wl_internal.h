@@ -91,6 +91,12 @@ hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
                        int32_t n_ppl, float4* d_seg, int* d_bad,
                        hipStream_t stream);
 
+// d-loop generation (Sec. 2.1) into d_x, d_y [n_loops][n_ppl] (n_ppl a
+// power of two, at most 8192): loops first_loop .. first_loop+n_loops-1 of
+// the Philox stream keyed by `seed`.
+hipError_t launch_generate(uint64_t seed, int64_t first_loop, int64_t n_loops, int32_t n_ppl,
+                           float* d_x, float* d_y, hipStream_t stream);
+
 hipError_t launch_average(int precision, int spin, const FieldArgs& f,
                           const float4* d_seg, const float* d_x,
                           const float* d_y, int32_t n_ppl,

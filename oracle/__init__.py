@@ -22,6 +22,10 @@ Contents
                          Simpson in x = 1/(1 + T/T_max) above; the rho_cm
                          integral of Eq. cylEA), with the locally-constant-
                          field (LCF) comparison of Sec. 6.
+  * ``correlation``   -- correlation coefficients between grid points over
+                         loops or groups (Sec. 4.2, Eq. corrcoef);
+                         ``regroup`` -- group sums of per-loop values under
+                         a permutation (randomised group assignment).
   * ``vloop_ensemble``-- an independent loop generator (i.i.d. Gaussian
                          increments, closed by subtracting their mean) that
                          samples the same discrete law as the d-loops of
@@ -400,6 +404,33 @@ def action(group_sums, n_loops, kind, eB0, lam, spin, m2, a, T_max, rho_max):
     return {"T": T, "rho": rho, "density": D, "density_mean": D.mean(axis=0),
             "density_err": sem(D), "action": A, "action_mean": A.mean(axis=0),
             "action_err": sem(A), "lcf_density": Dl, "lcf_action": rho_integral(Dl)}
+
+
+# ------------------------------------------------------ correlations, groups
+def correlation(values):
+    """Correlation coefficients between the columns of ``values`` (shape
+    (n_units, n_pts): per-loop w or group sums at each grid point) over the
+    units, Eq. corrcoef: rho_pq = <(W_p - <W_p>)(W_q - <W_q>)> divided by
+    the square roots of the two variances."""
+    X = np.asarray(values, dtype=np.float64)
+    Xc = X - X.mean(axis=0)
+    C = Xc.T @ Xc
+    d = np.sqrt(np.diag(C))
+    return C / np.outer(d, d)
+
+
+def regroup(per_unit, perm, n_groups):
+    """Group sums of per-unit values (n_units, n_pts) when the units are
+    taken in the order ``perm`` and cut into n_groups contiguous groups of
+    equal size (randomised group assignment, Sec. 4.2.3)."""
+    X = np.asarray(per_unit, dtype=np.float64)
+    n = X.shape[0]
+    if n % n_groups:
+        raise ValueError("n_groups must divide the number of units")
+    perm = np.asarray(perm)
+    if sorted(perm.tolist()) != list(range(n)):
+        raise ValueError("perm is not a permutation")
+    return X[perm].reshape(n_groups, n // n_groups, *X.shape[1:]).sum(axis=1)
 
 
 # ----------------------------------------------------------- closed forms

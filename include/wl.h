@@ -390,10 +390,47 @@ int wl_action(wl_ctx* ctx, const wl_action_spec* spec, const wl_field* field,
               int32_t spin, const double* group_sums, int32_t n_groups, int64_t n_loops,
               int32_t flags, const wl_action_out* out);
 
+/* ---- correlations between grid points and group reassignment (Sec. 4.2,
+ * Eq. corrcoef; Sec. 4.2.3, Grouping Worldlines) --------------------------
+ * Per-loop values come from an evaluation with one loop per group (see
+ * wl_ensemble_set_groups): its group sums [N_l][n_rho][n_T] are the w of
+ * each loop at each grid point. */
+
+/* Change the number of contiguous groups of an ensemble (1 <= n_groups,
+ * n_groups divides n_loops); later evaluations use it.
+ * Errors: WL_EINVAL. */
+int wl_ensemble_set_groups(wl_ens* ens, int32_t n_groups);
+
+/* Correlation coefficients between the n_pts columns of values [n_units]
+ * [n_pts] (per-loop w, or group sums, at each grid point) over the n_units
+ * rows: corr[p][q] = sum_k (x_kp - m_p)(x_kq - m_q) / sqrt(S_p S_q), m the
+ * column means and S_p = sum_k (x_kp - m_p)^2 (NaN for a constant column).
+ * corr is [n_pts][n_pts], exactly symmetric.  The Gram matrix runs on the
+ * FP64 matrix cores; deterministic.  flags WL_HOST_PTR: values and corr are
+ * host memory, WL_DEVICE_PTR: device memory.  n_units >= 2,
+ * 1 <= n_pts <= 16384.  Synchronous.  Errors: WL_EINVAL, WL_ENOMEM,
+ * WL_EHIP. */
+int wl_correlation(wl_ctx* ctx, const double* values, int64_t n_units, int32_t n_pts,
+                   int32_t flags, double* corr);
+
+/* Group sums under a reassignment of the units (loops) to groups:
+ * sums[g][p] = sum_{j < n_units/n_groups} per_unit[perm[g n_units/n_groups
+ * + j]][p], where perm is row point_perm[p] of perms [n_perms][n_units]
+ * (row 0 for every point if point_perm is NULL).  Independent random rows
+ * for different grid points give the paper's shuffled groups.  Each row of
+ * perms must be a permutation of 0 .. n_units-1 and n_groups must divide
+ * n_units.  flags as wl_correlation (all arrays host or all device); host
+ * arrays are validated, device ones are only range-checked (WL_EINVAL after
+ * the fact, out-of-range entries skipped).  Synchronous.
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_regroup(wl_ctx* ctx, const double* per_unit, int64_t n_units, int32_t n_pts,
+               const int64_t* perms, int32_t n_perms, const int32_t* point_perm,
+               int32_t n_groups, int32_t flags, double* sums);
+
 /* Kernel timing: when enabled, the main evaluation kernel of each
- * wl_average / wl_average_async / wl_discretisation call, and the
- * generation kernels of wl_ensemble_generate, are bracketed by HIP events on
- * the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.
+ * wl_average / wl_average_async / wl_discretisation call, the generation
+ * kernels of wl_ensemble_generate and the Gram kernel of wl_correlation are
+ * bracketed by HIP events on the ctx stream.  wl_set_timing(ctx, 1) also forgets earlier records.
  * wl_last_kernel_ms waits for the last recorded launch and returns its
  * duration in milliseconds; wl_kernel_ms_total waits for all of them and
  * returns the sum of their durations and their count.  Both return

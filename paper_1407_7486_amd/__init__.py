@@ -35,7 +35,8 @@ EXPORTS = (
     "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
     "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
-    "wl_ensemble_generate", "wl_ensemble_download",
+    "wl_ensemble_generate", "wl_ensemble_download", "wl_ensemble_set_groups",
+    "wl_correlation", "wl_regroup",
 )
 
 
@@ -118,6 +119,9 @@ _sigs = {
     "wl_action_grids": ([ctypes.POINTER(wl_action_spec), _vp, _vp], ctypes.c_int),
     "wl_action": ([_vp, ctypes.POINTER(wl_action_spec), ctypes.POINTER(wl_field), _i32, _vp,
                    _i32, _i64, _i32, ctypes.POINTER(wl_action_out)], ctypes.c_int),
+    "wl_ensemble_set_groups": ([_vp, _i32], ctypes.c_int),
+    "wl_correlation": ([_vp, _vp, _i64, _i32, _i32, _vp], ctypes.c_int),
+    "wl_regroup": ([_vp, _vp, _i64, _i32, _vp, _i32, _vp, _i32, _i32, _vp], ctypes.c_int),
     "wl_set_timing": ([_vp, _i32], ctypes.c_int),
     "wl_last_kernel_ms": ([_vp, ctypes.POINTER(_d)], ctypes.c_int),
     "wl_kernel_ms_total": ([_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
@@ -228,6 +232,36 @@ def wl_ensemble_download(ens, loop0, n_loops):
     if rc != WL_OK:
         raise WLError(rc, "wl_ensemble_download failed")
     return x, y
+
+
+def wl_ensemble_set_groups(ens, n_groups):
+    rc = _lib.wl_ensemble_set_groups(ens, int(n_groups))
+    if rc != WL_OK:
+        raise WLError(rc, "wl_ensemble_set_groups failed")
+
+
+def wl_correlation(ctx, values):
+    """Correlation matrix (n_pts, n_pts) of the columns of host values
+    (n_units, n_pts) over the rows."""
+    X = np.ascontiguousarray(values, dtype=np.float64)
+    n_units, n_pts = X.shape
+    out = np.zeros((n_pts, n_pts))
+    _check(_lib.wl_correlation(ctx, _ptr(X), n_units, n_pts, WL_HOST_PTR, _ptr(out)), ctx)
+    return out
+
+
+def wl_regroup(ctx, per_unit, perms, n_groups, point_perm=None):
+    """Group sums (n_groups, n_pts) of host per-unit values (n_units, n_pts)
+    under the permutations perms (n_perms, n_units); point_perm (n_pts,)
+    picks the permutation of each column (None: row 0 everywhere)."""
+    X = np.ascontiguousarray(per_unit, dtype=np.float64)
+    P = np.ascontiguousarray(np.atleast_2d(perms), dtype=np.int64)
+    Q = None if point_perm is None else np.ascontiguousarray(point_perm, dtype=np.int32)
+    n_units, n_pts = X.shape
+    out = np.zeros((n_groups, n_pts))
+    _check(_lib.wl_regroup(ctx, _ptr(X), n_units, n_pts, _ptr(P), P.shape[0], _ptr(Q),
+                           int(n_groups), WL_HOST_PTR, _ptr(out)), ctx)
+    return out
 
 
 def wl_ensemble_free(ens):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwl.so")
 SOURCES = ["wl_api.hip", "wl_kernels.hip", "wl_server.hip", "wl_action.hip",
-           "wl_generate.hip"]
+           "wl_generate.hip", "wl_corr.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

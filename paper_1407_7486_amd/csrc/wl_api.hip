@@ -232,13 +232,29 @@ void scatter_results(const wl_request& q, const BatchLayout& lay, int32_t i,
     memcpy(q.err, h_res + lay.sums_n + lay.pts_n + lay.pts_begin[i], n_pts * sizeof(double));
 }
 
+// Event pair for the next timed launch (created on first use).
+hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
+  if (ctx->n_timed == ctx->events.size()) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return e;
+    }
+    ctx->events.emplace_back(e0, e1);
+  }
+  *a = ctx->events[ctx->n_timed].first;
+  *b = ctx->events[ctx->n_timed].second;
+  return hipSuccess;
+}
+
 }  // namespace wl
 
 using namespace wl;
 
 extern "C" {
-
-static hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b);
 
 const char* wl_version(void) { return "wl 0.1 (gfx950)"; }
 
@@ -504,23 +520,6 @@ int wl_kernel_ms_total(wl_ctx* ctx, double* total_ms, int64_t* count) {
   return WL_OK;
 }
 
-// Event pair for the next timed launch (created on first use).
-static hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
-  if (ctx->n_timed == ctx->events.size()) {
-    hipEvent_t e0, e1;
-    hipError_t e = hipEventCreate(&e0);
-    if (e != hipSuccess) return e;
-    e = hipEventCreate(&e1);
-    if (e != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      return e;
-    }
-    ctx->events.emplace_back(e0, e1);
-  }
-  *a = ctx->events[ctx->n_timed].first;
-  *b = ctx->events[ctx->n_timed].second;
-  return hipSuccess;
-}
 
 // Enqueue one evaluation; grid and outputs are device memory.
 static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,

@@ -56,6 +56,8 @@ int check_field(wl_ctx* ctx, const wl_field* f, FieldArgs* a);
 int check_grid(wl_ctx* ctx, const double* rho, int32_t n_rho, const double* T, int32_t n_T);
 int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision);
 Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts);
+// Event pair for the next timed launch of ctx (pooled; created on first use).
+hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b);
 
 // Makes the context's device current for the duration of a call and
 // restores the caller's device afterwards.

@@ -35,7 +35,7 @@ KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
 # reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
 # re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": 18238163 * 1024 * 2 + 4096 * 1024 * 1}
+TRAFFIC = {"sech2_spinor_64k": None}
 
 
 def log(*a):
@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--workload", default="sech2_spinor_64k")
     ap.add_argument("--disc-steps", type=int, default=1,
                     help="timed calls of the discretisation estimate per mode (0: skip)")
+    ap.add_argument("--no-corr", action="store_true",
+                    help="skip the per-loop correlation matrix (Gram kernel on the matrix cores)")
     ap.add_argument("--no-generate", action="store_true",
                     help="skip timing the on-device loop generation")
     ap.add_argument("--cpu-loops", type=int, default=64,
@@ -277,6 +279,39 @@ def main():
             log(f"[bench] disc {name}: kernel {kd / nd:.1f} ms, "
                 f"{evals / (kd * 1e-3):.4e} seg/s")
 
+    corr = None
+    if not args.no_corr:
+        # per-loop w at every grid point (one loop per group), then the
+        # correlation matrix of the grid points over the loops
+        nl, npts = cfg["n_loops"], rho.size * T.size
+        wl.wl_ensemble_set_groups(ens, nl)
+        d_per = torch.empty((nl, npts), dtype=torch.float64, device=dev)
+        wl.wl_average_async(ctx, ens, fld, d_rho, d_T, spin, wl.WL_FP32C, None, None, d_per)
+        wl.wl_ensemble_set_groups(ens, G)
+        d_corr = torch.empty((npts, npts), dtype=torch.float64, device=dev)
+        import ctypes  # noqa: F401
+        fn = wl.raw_function("wl_correlation")
+        torch.cuda.synchronize()
+        rc = fn(ctx, d_per.data_ptr(), nl, npts, wl.WL_DEVICE_PTR, d_corr.data_ptr())  # warm-up
+        wl.wl_set_timing(ctx, True)
+        t0 = time.perf_counter()
+        rc = rc or fn(ctx, d_per.data_ptr(), nl, npts, wl.WL_DEVICE_PTR, d_corr.data_ptr())
+        dtc = time.perf_counter() - t0
+        kc, _ = wl.wl_kernel_ms_total(ctx)
+        wl.wl_set_timing(ctx, False)
+        if rc != 0:
+            raise RuntimeError(wl.wl_last_error(ctx))
+        flops = float(nl) * npts * (npts + 1)  # the symmetric Gram matrix
+        j3 = int(np.argmin(np.abs(T - 3.0)))
+        row = d_corr[rho.size // 2 * T.size + j3].cpu().numpy()
+        corr = {"n_units": nl, "n_pts": npts, "gram_kernel_ms": kc, "call_s": dtc,
+                "gram_tflops": flops / (kc * 1e-3) / 1e12, "peak_fp64_matrix_tflops": 78.6,
+                "frac": flops / (kc * 1e-3) / 78.6e12,
+                "corr_with_T3_min": float(np.nanmin(row)), "corr_with_T3_median": float(np.nanmedian(row))}
+        del d_per, d_corr
+        log(f"[bench] correlation {nl}x{npts}: Gram kernel {kc:.1f} ms, "
+            f"{flops / (kc * 1e-3) / 1e12:.1f} TFLOP/s FP64")
+
     gen = None
     if not args.no_generate:
         # the same ensemble generated on the device (d-loops, same Philox stream)
@@ -351,7 +386,7 @@ def main():
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
         "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "serve": serve,
-        "disc": disc, "generate": gen,
+        "disc": disc, "generate": gen, "correlation": corr,
     }
     print(json.dumps(out), flush=True)
 

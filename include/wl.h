@@ -225,7 +225,7 @@ typedef struct wl_server_config {
   int32_t slots;       /* batches in flight, 1..8 (default 2)               */
   int32_t max_batch;   /* requests per batch (default 1024)                 */
   size_t input_bytes;  /* per slot (default 8 MiB)                          */
-  size_t result_bytes; /* per slot (default 256 MiB)                        */
+  size_t result_bytes; /* per slot (default 512 MiB)                        */
 } wl_server_config;
 
 /* Start a server on an uploaded ensemble; cfg may be NULL for defaults.

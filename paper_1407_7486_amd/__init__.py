@@ -389,7 +389,7 @@ class Server:
     numpy outputs alive until the ticket is released."""
 
     def __init__(self, ctx, ens, slots=2, max_batch=1024, input_bytes=8 << 20,
-                 result_bytes=256 << 20):
+                 result_bytes=512 << 20):
         self.ctx, self.ens = ctx, ens
         self.G = wl_ensemble_info(ens)[2]
         cfg = wl_server_config(slots, max_batch, input_bytes, result_bytes)

@@ -128,16 +128,17 @@ wl::Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts) {
   wl::Sched s{};
   s.loops_per_group = e->n_loops / e->n_groups;
   s.n_chunks = (n_pts + wl::kWave - 1) / wl::kWave;
-  // Enough wavefronts for ~8 per SIMD (4 SIMDs per CU) so that the equal-
-  // cost items keep every SIMD busy until the end; split each group's loops
-  // into sub-ranges when groups x chunks alone fall short, at most 8 of them
-  // and of at least 8 loops each (the partial sums cost G n_sub n_pts
-  // doubles).  The rule depends only on the request and the ensemble, so a
-  // request is decomposed the same way alone and in a batch.
-  const int64_t target = (int64_t)ctx->num_cu * 4 * 8;
+  // Split each group's loops into sub-ranges until there are wavefronts for
+  // ~16 rounds of 8 per SIMD (4 SIMDs per CU): the items have equal cost,
+  // and with many short workgroups the hardware dispatcher keeps every SIMD
+  // busy to the end (with one or two rounds, the last one runs part-empty).
+  // At most 64 sub-ranges, of at least 8 loops each; the partial sums cost
+  // G n_sub n_pts doubles.  The rule depends only on the request and the
+  // ensemble, so a request is decomposed the same way alone and in a batch.
+  const int64_t target = (int64_t)ctx->num_cu * 4 * 8 * 16;
   const int64_t base = (int64_t)e->n_groups * s.n_chunks;
   int64_t n_sub = (target + base - 1) / base;
-  if (n_sub > 8) n_sub = 8;
+  if (n_sub > 64) n_sub = 64;
   if (n_sub > s.loops_per_group / 8) n_sub = s.loops_per_group / 8;
   if (n_sub < 1) n_sub = 1;
   s.loops_per_sub = (s.loops_per_group + n_sub - 1) / n_sub;

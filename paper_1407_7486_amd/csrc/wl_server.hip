@@ -255,7 +255,7 @@ int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg
   c.slots = 2;
   c.max_batch = 1024;
   c.input_bytes = (size_t)8 << 20;
-  c.result_bytes = (size_t)256 << 20;
+  c.result_bytes = (size_t)512 << 20;
   if (cfg) {
     if (cfg->slots < 1 || cfg->slots > 8) return wl::fail(ctx, WL_EINVAL, "slots must be 1..8");
     if (cfg->max_batch < 1) return wl::fail(ctx, WL_EINVAL, "max_batch must be >= 1");

@@ -397,7 +397,8 @@ int wl_action(wl_ctx* ctx, const wl_action_spec* spec, const wl_field* field,
  * each loop at each grid point. */
 
 /* Change the number of contiguous groups of an ensemble (1 <= n_groups,
- * n_groups divides n_loops); later evaluations use it.
+ * n_groups divides n_loops); later evaluations use it.  Not while a server
+ * (wl_server_create) runs on the ensemble or work on it is in flight.
  * Errors: WL_EINVAL. */
 int wl_ensemble_set_groups(wl_ens* ens, int32_t n_groups);
 

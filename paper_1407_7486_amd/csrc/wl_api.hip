@@ -770,6 +770,9 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
     case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q, 3, 4}; break;
     default: return fail(ctx, WL_EINVAL, "unknown sub-loop %d", subloop);
   }
+  if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
+    return fail(ctx, WL_EINVAL, "loop range [%lld, %lld) outside the ensemble",
+                (long long)loop0, (long long)(loop0 + n_loops));
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;

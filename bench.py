@@ -360,15 +360,20 @@ def main():
         oc = oracle.evaluate(xc, yc, c1["kind"], c1["eB0"], c1["lam"], rc_, tc_, c1["spin"],
                              c1["n_groups"], n_threads=0)
         dtc1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.evaluate(xc, yc, c1["kind"], c1["eB0"], c1["lam"], rc_, tc_, c1["spin"],
+                        c1["n_groups"], n_threads=1)
+        dtc1_1 = time.perf_counter() - t0
         mc, ec, _ = oracle.stats(oc["group_sums"], c1["n_loops"])
         wn = oracle.w_scalar_finite_n(tc_, c1["n_ppl"])
         cpu["const_scalar_1k"] = {
-            "seconds": dtc1, "threads": oracle.max_threads(),
+            "seconds": dtc1, "threads": oracle.max_threads(), "seconds_1_thread": dtc1_1,
             "segment_evals": c1["n_loops"] * c1["n_ppl"] * rc_.size * tc_.size,
             "max_dev_from_exact_finite_N_in_group_errors": float(np.max(np.abs(mc - wn) / ec)),
             "max_abs_dev_from_eBT_over_sinh": float(np.max(np.abs(
                 mc - oracle.w_scalar_continuum(c1["eB0"] * tc_))))}
-        log(f"[bench] cpu oracle constant-field workload {dtc1:.2f} s")
+        log(f"[bench] cpu oracle constant-field workload {dtc1:.2f} s "
+            f"({oracle.max_threads()} threads), {dtc1_1:.2f} s on 1 thread")
 
     wl.wl_ensemble_free(ens)
     serve = None

@@ -203,12 +203,14 @@ int wlo_evaluate(const double* X, const double* Y, int64_t n_loops, int32_t n,
     wbuf = (double*)malloc(sizeof(double) * (size_t)(n_loops * npts));
     if (!wbuf) return -2;
   }
+  /* a thread count for this call only (the process-wide default stays) */
+  int nt = 1;
 #ifdef _OPENMP
-  if (n_threads > 0) omp_set_num_threads(n_threads);
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
   (void)n_threads;
 #endif
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
   for (int64_t l = 0; l < n_loops; ++l) {
     const double* yx = X + l * n;
     const double* yy = Y + l * n;

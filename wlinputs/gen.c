@@ -132,12 +132,14 @@ int wli_dloop_ensemble_f32(uint64_t seed, int64_t first_loop, int64_t n_loops,
                            int32_t n_threads) {
   if (!is_pow2(n_ppl) || n_loops < 0 || first_loop < 0) return -1;
   int failed = 0;
+  /* a thread count for this call only (the process-wide default stays) */
+  int nt = 1;
 #ifdef _OPENMP
-  if (n_threads > 0) omp_set_num_threads(n_threads);
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
   (void)n_threads;
 #endif
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
   {
     double* z = (double*)malloc(sizeof(double) * 2 * (size_t)n_ppl);
     double* x = (double*)malloc(sizeof(double) * (size_t)n_ppl);

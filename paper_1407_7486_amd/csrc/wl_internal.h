@@ -10,11 +10,13 @@ namespace wl {
 // Per-segment unit-loop quantities used by the FP32 kernels, one float4 per
 // segment i -> i+1 of a unit loop y (indices mod N):
 //   x = m_x        = (y_i^x + y_{i+1}^x)/2       unit midpoint, x
-//   y = m_y        = (y_i^y + y_{i+1}^y)/2       unit midpoint, y
+//   y = m_y^2      = ((y_i^y + y_{i+1}^y)/2)^2   unit midpoint, y, squared
 //   z = d_y        = y_{i+1}^y - y_i^y           unit step, y
 //   w = c          = y_i^x y_{i+1}^y - y_i^y y_{i+1}^x   unit cross product
 // so that for the scaled, shifted loop (rho_cm + s y^x, s y^y), s = sqrt(T):
-//   midpoint = (rho_cm + s m_x, s m_y),   cross_i = rho_cm s d_y + T c.
+//   midpoint = (rho_cm + s m_x, s m_y),   cross_i = rho_cm s d_y + T c,
+// and its squared radius is (rho_cm + s m_x)^2 + T m_y^2 (m_y only enters
+// squared, so the square is stored: one multiply less per segment).
 
 // Work decomposition of one evaluation: one wavefront per item
 // (group g, loop sub-range `sub`, chunk of 64 grid points).

@@ -14,7 +14,7 @@
 // Arithmetic per segment (Sec. 3.2.1, Eqs. rhoi..Ci with the midpoint rule
 // t = 1/2, and Sec. 3.2.2, Eq. Wfermfpl), from the unit midpoint m, the unit
 // step d and the unit cross product c of the segment:
-//   midpoint (rho_cm + s m_x, s m_y),  rho^2 = its squared radius
+//   midpoint (rho_cm + s m_x, s m_y),  rho^2 = (rho_cm + s m_x)^2 + T m_y^2
 //   cross = U d_y + R c          (U = rho_cm s, R = s^2 = T, s = sqrt(T))
 //   phase += cross * qa(rho^2),  spin += qb(rho^2)
 // Forming the midpoint (instead of expanding rho^2 around rho_cm^2) keeps
@@ -215,11 +215,10 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y, d_y, c)
+  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y^2, d_y, c)
     const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
                           : fmaf(c.s_hi, s.x, c.rho_hi);
-    const float my = c.s_hi * s.y;
-    const float r2 = fmaf(mx, mx, fmaf(my, my, 1e-30f));
+    const float r2 = fmaf(mx, mx, fmaf(c.R, s.y, 1e-30f));
     const float cr = fmaf(c.R, s.w, c.U * s.z);
     float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
@@ -713,7 +712,7 @@ __device__ __forceinline__ float4 seg_quantities(float x0f, float y0f, float x1f
   const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
   float4 o;
   o.x = (float)(0.5 * (x0 + x1));
-  o.y = (float)(0.5 * (y0 + y1));
+  o.y = (float)(0.25 * (y0 + y1) * (y0 + y1));
   o.z = (float)(y1 - y0);
   o.w = (float)(x0 * y1 - y0 * x1);
   return o;

@@ -52,7 +52,8 @@ struct FieldArgs {
   // FP64 path
   double inv_lam_d, inv_lam2_d, lam2_d;
   // epilogue: Phi = cphi * sum_i cross_i qa_i ; S = cspin (T/N) sum_i qb_i
-  double cphi, cspin;
+  // (cphi32 for the FP32 paths, whose sech^2 qa is in scaled units)
+  double cphi, cspin, cphi32;
 };
 
 // Header of a batch in device memory, followed (at kBatchDescOffset) by

@@ -39,6 +39,12 @@ namespace {
 
 constexpr float kLn2f = 0.69314718055994531f;
 constexpr double kLn2 = 0.69314718055994530942;
+// sech^2 FP32 path in scaled units: geometry multiplied by
+// gs = 2 log2(e)/lambda, so that r2 = (2 u log2 e)^2 (u = rho/lambda)
+constexpr double kTwoLog2e = 2.8853900817779268147;
+constexpr float kSech2ThrS = (float)(kTwoLog2e * kTwoLog2e);           // u < 1
+constexpr float kSech2Vs = (float)(1.0 / (kTwoLog2e * kTwoLog2e));     // r2 -> u^2
+constexpr float kSech2Ps = (float)(1.0 / (kLn2 * kTwoLog2e * kTwoLog2e));
 
 enum { kConst = 0, kSech2 = 1, kGauss = 2, kRational = 3 };
 
@@ -62,7 +68,8 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 // qa: phase weight, qb: spin integrand, as functions of rho^2 (FP32,
 // hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
 // Units (the epilogue constants cphi, cspin restore them):
-//   SECH2  qa = g/(eB0 lambda^2)    qb = sech^2(u)/4
+//   SECH2  qa = g/(eB0 lambda^2 ln2 gs^2), gs = 2 log2(e)/lambda, with r2
+//          in units scaled by gs          qb = sech^2(u)/4
 //   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
 //   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
 // r2 > 0 (the caller adds 1e-30).
@@ -75,23 +82,27 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     qa = 1.0f;
     qb = 1.0f;
   } else if constexpr (KIND == kSech2) {
-    // u = rho/lambda, E = exp(-2u), sech^2 u = 4 E/(1+E)^2;
-    // g/eB0 = (u tanh u - ln cosh u)/u^2 = (ln2 - ln(1+E) - 2uE/(1+E))/u^2,
-    // whose terms cancel below u = 1: there a polynomial in u^2 is used.
-    const float rs = __builtin_amdgcn_rsqf(r2);  // 1/rho
-    const float rho = r2 * rs;
-    const float E = __builtin_amdgcn_exp2f(rho * f.exp2_scale);
+    // r2 is in scaled units, r2 = t^2 with t = 2 u log2(e) and u = rho/lambda
+    // (the geometry multiplied by gs = 2 log2(e)/lambda).  Then E = exp(-2u)
+    // = 2^-t, sech^2 u = 4 E/(1+E)^2, and since
+    // u tanh u - ln cosh u = ln2 (1 - log2(1+E) - t E/(1+E)) the phase weight
+    // is qa = (1 - log2(1+E) - t E/(1+E)) / r2: g/(eB0 lambda^2) divided by
+    // ln2 gs^2 (the FP32 epilogue constant cphi32 carries that factor).  The
+    // terms cancel below u = 1, where a polynomial in u^2 is used.
+    const float q = __builtin_amdgcn_rsqf(r2);  // 1/t
+    const float t = r2 * q;
+    const float E = __builtin_amdgcn_exp2f(-t);
     const float opE = 1.0f + E;
     const float ip = __builtin_amdgcn_rcpf(opE);
     const float Eip = E * ip;
     qb = Eip * ip;
-    if (r2 < f.thr) {
-      const float v = r2 * f.inv_lam2;
-      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * f.inv_lam2;
+    if (r2 < kSech2ThrS) {
+      const float v = r2 * kSech2Vs;
+      qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * kSech2Ps;
     } else {
       const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
-      const float h = fmaf(-kLn2f, lg, kLn2f) - (rho * f.two_inv_lam) * Eip;
-      qa = (h * rs) * rs;
+      const float h = fmaf(-t, Eip, 1.0f - lg);
+      qa = (h * q) * q;
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
@@ -191,15 +202,23 @@ struct LaneF32 {
   float rho_hi, rho_lo;  // rho_cm = hi + lo
   float s_hi;            // sqrt(T)
   float R, U;            // T, rho_cm sqrt(T)
+  // sech^2: the same geometry scaled by gs = 2 log2(e)/lambda
+  float rho_s_hi, rho_s_lo, s_s, R_s;
 };
 
-__device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T) {
+__device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
+                                               const FieldArgs& f) {
   LaneF32 c;
   c.rho_hi = (float)rho;
   c.rho_lo = (float)(rho - (double)c.rho_hi);
   c.s_hi = (float)s;
   c.R = (float)T;
   c.U = (float)(rho * s);
+  const double gs = kTwoLog2e * f.inv_lam_d;
+  c.rho_s_hi = (float)(rho * gs);
+  c.rho_s_lo = (float)(rho * gs - (double)c.rho_s_hi);
+  c.s_s = (float)(s * gs);
+  c.R_s = (float)(T * gs * gs);
   return c;
 }
 
@@ -216,9 +235,16 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
   auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y^2, d_y, c)
-    const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
-                          : fmaf(c.s_hi, s.x, c.rho_hi);
-    const float r2 = fmaf(mx, mx, fmaf(c.R, s.y, 1e-30f));
+    float r2;  // squared radius of the midpoint (sech^2: in scaled units)
+    if constexpr (KIND == kSech2) {
+      const float mx = COMP ? fmaf(c.s_s, s.x, c.rho_s_hi) + c.rho_s_lo
+                            : fmaf(c.s_s, s.x, c.rho_s_hi);
+      r2 = fmaf(mx, mx, fmaf(c.R_s, s.y, 1e-30f));
+    } else {
+      const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
+                            : fmaf(c.s_hi, s.x, c.rho_hi);
+      r2 = fmaf(mx, mx, fmaf(c.R, s.y, 1e-30f));
+    }
     const float cr = fmaf(c.R, s.w, c.U * s.z);
     float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
@@ -328,7 +354,7 @@ template <bool SPIN, int PREC>
 __device__ __forceinline__ double epilogue(double A, double B, double T,
                                            int32_t n, const FieldArgs& f,
                                            double& phi, double& S) {
-  phi = f.cphi * A;
+  phi = (PREC == 2 ? f.cphi : f.cphi32) * A;
   S = SPIN ? f.cspin * (T / n) * B : 0.0;
   return wval<SPIN, PREC>(phi, S);
 }
@@ -345,7 +371,8 @@ __device__ __forceinline__ void disc_levels(double Ac, double Bc, double As, dou
                                             double At, double Bt, double T, int32_t h,
                                             int32_t q, const FieldArgs& f, bool full,
                                             double& w1, double& w2, double& w4) {
-  const double pc = f.cphi * Ac, ps = f.cphi * As, pt = f.cphi * At;
+  const double cp = PREC == 2 ? f.cphi : f.cphi32;
+  const double pc = cp * Ac, ps = cp * As, pt = cp * At;
   double sc = 0.0, ss = 0.0, st = 0.0;
   if constexpr (SPIN) {
     sc = f.cspin * (T / h) * Bc;
@@ -399,7 +426,7 @@ __device__ __forceinline__ void run_item(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  const LaneF32 c = lane_consts(rho, s, T);
+  const LaneF32 c = lane_consts(rho, s, T, f);
 
   double acc = 0.0;
   for (int64_t l = l0; l < l1; ++l) {
@@ -449,7 +476,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  const LaneF32 c = lane_consts(rho, s, T);
+  const LaneF32 c = lane_consts(rho, s, T, f);
 
   double acc = 0.0;
   for (int64_t k = 0; k < sc.loops_per_sub; ++k) {
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  const LaneF32 c = lane_consts(rho, s, T);
+  const LaneF32 c = lane_consts(rho, s, T, f);
   const int32_t h = n_ppl / 2, q = n_ppl / 4;
 
   double acc1 = 0.0, acc2 = 0.0, acc4 = 0.0;
@@ -689,7 +716,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   const double rho = rho_g[pp / n_T];
   const double T = T_g[pp % n_T];
   const double s = sqrt(T);
-  const LaneF32 c = lane_consts(rho, s, T);
+  const LaneF32 c = lane_consts(rho, s, T, f);
   double A, B, phi, S;
   if constexpr (PREC == 2) {
     loop_sums_f64<KIND, SPIN>(X + l * n_ppl + sl.x_off, Y + l * n_ppl + sl.x_off, sl.x_stride,

@@ -94,9 +94,9 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
       a->cspin = f->eB0 * l * l * l * l;
       break;
   }
-  // FP32 sech^2 works in units scaled by gs = 2 log2(e)/lambda (qa / (ln2 gs^2))
-  const double gs = 2.8853900817779268147 / l;
-  a->cphi32 = f->kind == WL_SECH2 ? a->cphi * 0.69314718055994530942 * gs * gs : a->cphi;
+  // FP32 sech^2 works in units scaled by gs = 2 log2(e)/lambda: its qa is
+  // divided by ln2 gs^2 and its cross product multiplied by gs^2
+  a->cphi32 = f->kind == WL_SECH2 ? a->cphi * 0.69314718055994530942 : a->cphi;
   a->exp2_scale = (float)e2;
   a->exp2_scale_lo = (float)(e2 - (double)a->exp2_scale);
   return WL_OK;

@@ -69,7 +69,8 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 // hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
 // Units (the epilogue constants cphi, cspin restore them):
 //   SECH2  qa = g/(eB0 lambda^2 ln2 gs^2), gs = 2 log2(e)/lambda, with r2
-//          in units scaled by gs          qb = sech^2(u)/4
+//          (and the caller's cross product) in units scaled by gs
+//          qb = sech^2(u)/4
 //   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
 //   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
 // r2 > 0 (the caller adds 1e-30).
@@ -87,8 +88,10 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     // = 2^-t, sech^2 u = 4 E/(1+E)^2, and since
     // u tanh u - ln cosh u = ln2 (1 - log2(1+E) - t E/(1+E)) the phase weight
     // is qa = (1 - log2(1+E) - t E/(1+E)) / r2: g/(eB0 lambda^2) divided by
-    // ln2 gs^2 (the FP32 epilogue constant cphi32 carries that factor).  The
-    // terms cancel below u = 1, where a polynomial in u^2 is used.
+    // ln2 gs^2.  The cross product is formed in the same units (gs^2 times
+    // the unscaled one), so gs^2 cancels in the product and the FP32
+    // epilogue constant cphi32 carries ln2.  The terms cancel below u = 1,
+    // where a polynomial in u^2 is used.
     const float q = __builtin_amdgcn_rsqf(r2);  // 1/t
     const float t = r2 * q;
     const float E = __builtin_amdgcn_exp2f(-t);
@@ -100,9 +103,10 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
       const float v = r2 * kSech2Vs;
       qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * kSech2Ps;
     } else {
-      const float lg = __builtin_amdgcn_logf(opE);  // log2(1+E)
-      const float h = fmaf(-t, Eip, 1.0f - lg);
-      qa = (h * q) * q;
+      // qa = (1 - hp) q^2 with hp = log2(1+E) + t E/(1+E), q^2 = 1/r2
+      const float hp = fmaf(t, Eip, __builtin_amdgcn_logf(opE));
+      const float q2 = q * q;
+      qa = fmaf(-hp, q2, q2);
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
@@ -202,8 +206,10 @@ struct LaneF32 {
   float rho_hi, rho_lo;  // rho_cm = hi + lo
   float s_hi;            // sqrt(T)
   float R, U;            // T, rho_cm sqrt(T)
-  // sech^2: the same geometry scaled by gs = 2 log2(e)/lambda
-  float rho_s_hi, rho_s_lo, s_s, R_s;
+  // sech^2: the same geometry scaled by gs = 2 log2(e)/lambda, all derived
+  // from the rounded scaled sqrt(T) so that the scaled loop is one similar
+  // figure (R_s = s_s^2, U_s = rho_s s_s up to one rounding each)
+  float rho_s_hi, rho_s_lo, s_s, R_s, U_s;
 };
 
 __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
@@ -218,7 +224,8 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
   c.rho_s_hi = (float)(rho * gs);
   c.rho_s_lo = (float)(rho * gs - (double)c.rho_s_hi);
   c.s_s = (float)(s * gs);
-  c.R_s = (float)(T * gs * gs);
+  c.R_s = (float)((double)c.s_s * (double)c.s_s);
+  c.U_s = (float)(((double)c.rho_s_hi + (double)c.rho_s_lo) * (double)c.s_s);
   return c;
 }
 
@@ -235,17 +242,20 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
   constexpr bool kSpinSum = SPIN && KIND != kConst;
   float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
   auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y^2, d_y, c)
-    float r2;  // squared radius of the midpoint (sech^2: in scaled units)
+    // squared radius of the midpoint and cross product (sech^2: both in
+    // scaled units)
+    float r2, cr;
     if constexpr (KIND == kSech2) {
       const float mx = COMP ? fmaf(c.s_s, s.x, c.rho_s_hi) + c.rho_s_lo
                             : fmaf(c.s_s, s.x, c.rho_s_hi);
       r2 = fmaf(mx, mx, fmaf(c.R_s, s.y, 1e-30f));
+      cr = fmaf(c.R_s, s.w, c.U_s * s.z);
     } else {
       const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
                             : fmaf(c.s_hi, s.x, c.rho_hi);
       r2 = fmaf(mx, mx, fmaf(c.R, s.y, 1e-30f));
+      cr = fmaf(c.R, s.w, c.U * s.z);
     }
-    const float cr = fmaf(c.R, s.w, c.U * s.z);
     float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
     pa = fmaf(cr, qa, pa);

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import wlinputs
-from wl_tol import TOL, mean_scales, phase_limit
+from wl_tol import TOL, mean_random_scale, mean_scales, phase_limit
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,9 @@ def test_precision_stress_table(setup):
                                 per_loop=True)
             o_mean, _, _ = oracle.stats(o["group_sums"], N_LOOPS)
             m_s, _ = mean_scales(o["w"], o["spin"], G)
+            # random per-loop phase errors carried to the mean (5 sigma at a
+            # per-loop relative phase error of the mean tolerance's size)
+            m_r, _ = mean_random_scale(o["phase"], o["spin"], spin, G)
             fld = wl.field(1, fcfg["eB0"], fcfg["lam"])
             row = [fcfg["eB0"], fcfg["lam"], spin]
             for prec in (1, 0, 2):  # plain FP32, FP32C, FP64
@@ -54,7 +57,8 @@ def test_precision_stress_table(setup):
                 e_m = float((np.abs(mean - o_mean) / m_s).max())
                 row += [e_ph, f_ph, e_sp, e_m]
                 if prec in worst:
-                    worst[prec] = max(worst[prec], e_m / TOL[prec]["mean"])
+                    lim = TOL[prec]["mean"] * (m_s + 5.0 * m_r)
+                    worst[prec] = max(worst[prec], float((np.abs(mean - o_mean) / lim).max()))
                     lim = phase_limit(prec, o["phase"], o["phase_abs"], N_PPL)
                     assert (dph <= lim).all(), (fcfg, spin, prec, float((dph / lim).max()))
             rows.append(row)
@@ -67,6 +71,7 @@ def test_precision_stress_table(setup):
     print(" | ".join(hdr))
     for r in rows:
         print(" | ".join(f"{v:g}" if i < 3 else f"{v:.2e}" for i, v in enumerate(r)))
-    print(f"worst mean error / tolerance: fp32c {worst[0]:.3g}, fp64 {worst[2]:.3g}")
+    print(f"worst mean error / tolerance (M_S plus 5x the random phase spread): "
+          f"fp32c {worst[0]:.3g}, fp64 {worst[2]:.3g}")
     sys.stdout.flush()
     assert worst[0] <= 1.0 and worst[2] <= 1.0

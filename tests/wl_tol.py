@@ -16,7 +16,12 @@ For scalar loops (S = 0, |w| <= 1) that is at most 1e-6 absolute.  For
 spinors, FP32 carries the loop geometry, T and the field scales to relative
 precision u = 2^-24, so S has an error of order u S that cosh turns into a
 relative error of order u S tanh(S) in w: the mean is ill-conditioned by the
-factor S (the fermion problem, Sec. 4.3), and the scale includes it.
+factor S (the fermion problem, Sec. 4.3), and the scale includes it.  Where a
+few loops with large cosh S dominate a spinor mean, their random per-loop
+phase errors also reach the mean unaveraged; mean_random_scale() gives that
+spread for a per-loop relative phase error of 1, and the precision-stress
+test adds 5 times it at a per-loop phase error of 1e-6 (twice the measured
+FP32C rms).
 
 WL_FP32 (plain sums) is a precision-study mode and only has to agree to
 1e-3 relative.
@@ -70,6 +75,22 @@ def mean_scales(o_w, o_spin, n_groups):
     a = np.abs(o_w) * np.maximum(1.0, np.abs(o_spin))
     nl = a.shape[0]
     return a.mean(axis=0), a.reshape(n_groups, nl // n_groups, *a.shape[1:]).sum(axis=1)
+
+
+def mean_random_scale(o_phase, o_spin, spin, n_groups):
+    """Spread of the mean (and of the group sums) from independent random
+    per-loop phase errors of relative size 1 (Sec. 4.3: a spinor mean is
+    dominated by the few loops with the largest cosh S, so their phase errors
+    carry over to the mean without averaging):
+    R = (1/N_l) sqrt(sum_l (sin(Phi_l) cosh(S_l) max(1, |Phi_l|))^2), and the
+    per-group sums sqrt(sum_{l in g} (...)^2).  Shapes as mean_scales."""
+    d = np.abs(np.sin(o_phase)) * np.maximum(1.0, np.abs(o_phase))
+    if spin:
+        d = d * np.cosh(o_spin)
+    nl = d.shape[0]
+    d2 = d * d
+    return (np.sqrt(d2.sum(axis=0)) / nl,
+            np.sqrt(d2.reshape(n_groups, nl // n_groups, *d.shape[1:]).sum(axis=1)))
 
 
 def check_means(prec, mean, sums, o_mean, o_sums, o_w_abs_mean, o_w_abs_group):

@@ -22,9 +22,9 @@ METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p9
 # kernel, in FP32 lane-op slots: every FP32 VALU instruction of the
 # formulation counts 1 and every transcendental (exp, log, rcp, rsq) counts 4
 # (measured on MI355X: a transcendental costs ~4 FMA issue slots).  The sech^2
-# count is the far-from-axis branch (22 instructions, 4 of them
+# count is the far-from-axis branch (21 instructions, 4 of them
 # transcendental, with the block sums' compensation amortised).
-SLOTS_FP32C = {("sech2", 1): 34, ("sech2", 0): 32, ("gauss", 1): 22,
+SLOTS_FP32C = {("sech2", 1): 33, ("sech2", 0): 31, ("gauss", 1): 22,
                ("gauss", 0): 20, ("rational", 1): 16, ("rational", 0): 14,
                ("const", 1): 4, ("const", 0): 4}
 # FP32 VALU peak: 157.3 TFLOP/s / 2 flop per FMA = 256 CUs x 128 FP32
@@ -35,7 +35,7 @@ KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
 # reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
 # re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": None}
+TRAFFIC = {"sech2_spinor_64k": 15060283 * 1024 * 2 + 65536 * 1024 * 1}
 
 
 def log(*a):

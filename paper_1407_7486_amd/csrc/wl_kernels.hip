@@ -231,9 +231,11 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
 
 // Phase and spin sums of one loop for this lane's grid point (FP32 path).
 // `seg` is wave-uniform.  Returns sum cross*qa and sum qb in FP64.
-// Compensated mode: each block of 8 segments is summed plainly and the
-// block sums enter Kahan sums, so the long sum over the loop carries no
-// error growth with N; plain mode sums every term directly.
+// Compensated mode: each block of 16 segments (two fetches of 8, not
+// unrolled together, which keeps the register count at the 8-segment
+// kernel's) is summed plainly and the block sums enter Kahan sums, so the
+// long sum over the loop carries no error growth with N; plain mode sums
+// every term directly.
 template <int KIND, bool SPIN, bool COMP>
 __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               int32_t n, const LaneF32& c,
@@ -262,6 +264,21 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
     if constexpr (kSpinSum) pb += qb;
   };
   int32_t i = 0;
+  if constexpr (COMP) {
+    for (; i + 16 <= n; i += 16) {
+      float pa = 0.0f, pb = 0.0f;
+#pragma unroll 1
+      for (int half = 0; half < 2; ++half) {
+        float4 sv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sv[k] = seg[i + 8 * half + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
+      }
+      kahan_add(as, ac, pa);
+      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+    }
+  }
   for (; i + 8 <= n; i += 8) {
     // fetch the block's 8 segments up front so that one wait covers them
     float4 sv[8];

@@ -22,11 +22,12 @@ METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p9
 # kernel, in FP32 lane-op slots: every FP32 VALU instruction of the
 # formulation counts 1 and every transcendental (exp, log, rcp, rsq) counts 4
 # (measured on MI355X: a transcendental costs ~4 FMA issue slots).  The sech^2
-# count is the far-from-axis branch (21 instructions, 4 of them
-# transcendental, with the block sums' compensation amortised).
-SLOTS_FP32C = {("sech2", 1): 33, ("sech2", 0): 31, ("gauss", 1): 22,
-               ("gauss", 0): 20, ("rational", 1): 16, ("rational", 0): 14,
-               ("const", 1): 4, ("const", 0): 4}
+# count is the far-from-axis branch (20.5 instructions, 4 of them
+# transcendental, with the compensation of the 16-segment block sums
+# amortised: 4 instructions per Kahan update, one per block and sum).
+SLOTS_FP32C = {("sech2", 1): 32.5, ("sech2", 0): 31.25, ("gauss", 1): 21.5,
+               ("gauss", 0): 19.75, ("rational", 1): 15.5, ("rational", 0): 13.75,
+               ("const", 1): 3.25, ("const", 0): 3.25}
 # FP32 VALU peak: 157.3 TFLOP/s / 2 flop per FMA = 256 CUs x 128 FP32
 # lanes/clk x 2.4 GHz lane-ops per second.
 PEAK_OPS = 256 * 128 * 2.4e9
@@ -35,7 +36,7 @@ KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
 # reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
 # re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": None}
+TRAFFIC = {"sech2_spinor_64k": 14504730 * 1024 * 2 + 65536 * 1024}
 
 
 def log(*a):

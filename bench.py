@@ -19,15 +19,16 @@ sys.path.insert(0, ROOT)
 METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p99 ms"
 
 # Algorithmic VALU cost of one segment evaluation in the FP32 compensated
-# kernel, in FP32 lane-op slots: every FP32 VALU instruction of the
-# formulation counts 1 and every transcendental (exp, log, rcp, rsq) counts 4
-# (measured on MI355X: a transcendental costs ~4 FMA issue slots).  The sech^2
-# count is the far-from-axis branch (20.5 instructions, 4 of them
-# transcendental, with the compensation of the 16-segment block sums
-# amortised: 4 instructions per Kahan update, one per block and sum).
-SLOTS_FP32C = {("sech2", 1): 32.5, ("sech2", 0): 31.25, ("gauss", 1): 21.5,
-               ("gauss", 0): 19.75, ("rational", 1): 15.5, ("rational", 0): 13.75,
-               ("const", 1): 3.25, ("const", 0): 3.25}
+# kernel, in FP32 lane-op slots: every VALU instruction of the formulation
+# (multiply-adds fused) counts 1 and every transcendental (exp, log, rcp,
+# rsq) counts 4 (measured on MI355X: a transcendental costs ~4 FMA issue
+# slots).  The sech^2 spinor count is the far-from-axis branch: 14
+# instructions + 4 transcendentals, plus the FP64 accumulation of the
+# 32-segment block sums amortised (a conversion and an add per block and
+# sum: 3 x 2 / 32).
+SLOTS_FP32C = {("sech2", 1): 30.1875, ("sech2", 0): 29.125, ("gauss", 1): 20.1875,
+               ("gauss", 0): 19.125, ("rational", 1): 13.1875, ("rational", 0): 12.125,
+               ("const", 1): 2.125, ("const", 0): 2.125}
 # FP32 VALU peak: 157.3 TFLOP/s / 2 flop per FMA = 256 CUs x 128 FP32
 # lanes/clk x 2.4 GHz lane-ops per second.
 PEAK_OPS = 256 * 128 * 2.4e9
@@ -36,7 +37,7 @@ KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
 # reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
 # re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": 14504730 * 1024 * 2 + 65536 * 1024}
+TRAFFIC = {"sech2_spinor_64k": 15006693 * 1024 * 2 + 65536 * 1024}
 
 
 def log(*a):

@@ -71,8 +71,9 @@ typedef struct wl_field {
 } wl_field;
 
 /* ---- precision modes ---------------------------------------------------
- * WL_FP32C  FP32 segment arithmetic with compensated (Kahan) phase and
- *           spin sums; FP64 per-loop epilogue and FP64 group sums.
+  * WL_FP32C  FP32 segment arithmetic; phase and spin sums compensated (FP32
+ *           sums over blocks of 32 segments, the block sums accumulated in
+ *           FP64); FP64 per-loop epilogue and FP64 group sums.
  * WL_FP32   the same with plain FP32 sums (precision-study mode).
  * WL_FP64   FP64 throughout.                                               */
 #define WL_FP32C 0

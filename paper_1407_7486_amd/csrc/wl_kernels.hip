@@ -187,21 +187,6 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
   }
 }
 
-// --------------------------------------------------- compensated sums
-__device__ __forceinline__ void kahan_fma(float& s, float& c, float a, float b) {
-  const float y = fmaf(a, b, -c);
-  const float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float a) {
-  const float y = a - c;
-  const float t = s + y;
-  c = (t - s) - y;
-  s = t;
-}
-
 struct LaneF32 {
   float rho_hi, rho_lo;  // rho_cm = hi + lo
   float s_hi;            // sqrt(T)
@@ -231,52 +216,67 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
 
 // Phase and spin sums of one loop for this lane's grid point (FP32 path).
 // `seg` is wave-uniform.  Returns sum cross*qa and sum qb in FP64.
-// Compensated mode: each block of 16 segments (two fetches of 8, not
+// The cross product cross_i = R c_i + U d_y,i (R = T, U = rho_cm sqrt(T);
+// sech^2: their scaled values) is not formed per segment: the two sums
+// sum c_i qa_i and sum d_y,i qa_i are kept apart and combined once per loop
+// in FP64, one instruction less per segment.  (Where a loop crosses the axis
+// far from its centre the two parts cancel within a segment, so each carries
+// a rounding error of the size of the larger part: about twice the phase
+// error of the combined product there, still far inside FP32C's bar.)
+// Compensated mode: each block of 32 segments (four fetches of 8, not
 // unrolled together, which keeps the register count at the 8-segment
-// kernel's) is summed plainly and the block sums enter Kahan sums, so the
-// long sum over the loop carries no error growth with N; plain mode sums
-// every term directly.
+// level) is summed plainly in FP32 and the block sums accumulate in FP64, so
+// the long sum over the loop carries no error growth with N; plain mode
+// sums every term in FP32.
 template <int KIND, bool SPIN, bool COMP>
 __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               int32_t n, const LaneF32& c,
                                               const FieldArgs& f, double& A,
                                               double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
-  float as = 0.0f, ac = 0.0f, bs = 0.0f, bc = 0.0f;
-  auto term = [&](const float4 s, float& pa, float& pb) {  // s = (m_x, m_y^2, d_y, c)
-    // squared radius of the midpoint and cross product (sech^2: both in
-    // scaled units)
-    float r2, cr;
+  struct Acc {
+    float c, d, b;  // sum c qa, sum d_y qa, sum qb
+  };
+  auto term = [&](const float4 s, Acc& p) {  // s = (m_x, m_y^2, d_y, c)
+    // squared radius of the midpoint (sech^2: in scaled units)
+    float r2;
     if constexpr (KIND == kSech2) {
       const float mx = COMP ? fmaf(c.s_s, s.x, c.rho_s_hi) + c.rho_s_lo
                             : fmaf(c.s_s, s.x, c.rho_s_hi);
       r2 = fmaf(mx, mx, fmaf(c.R_s, s.y, 1e-30f));
-      cr = fmaf(c.R_s, s.w, c.U_s * s.z);
-    } else {
+    } else if constexpr (KIND != kConst) {
       const float mx = COMP ? fmaf(c.s_hi, s.x, c.rho_hi) + c.rho_lo
                             : fmaf(c.s_hi, s.x, c.rho_hi);
       r2 = fmaf(mx, mx, fmaf(c.R, s.y, 1e-30f));
-      cr = fmaf(c.R, s.w, c.U * s.z);
+    } else {
+      r2 = 1.0f;
     }
     float qa, qb;
     field_f32<KIND, COMP>(r2, f, qa, qb);
-    pa = fmaf(cr, qa, pa);
-    if constexpr (kSpinSum) pb += qb;
+    p.c = fmaf(s.w, qa, p.c);
+    p.d = fmaf(s.z, qa, p.d);
+    if constexpr (kSpinSum) p.b += qb;
   };
+  double dc = 0.0, dd = 0.0, db = 0.0;  // compensated mode: FP64 block sums
+  auto add_block = [&](const Acc& p) {
+    dc += (double)p.c;
+    dd += (double)p.d;
+    if constexpr (kSpinSum) db += (double)p.b;
+  };
+  Acc s_ = {0.0f, 0.0f, 0.0f};  // plain mode: FP32 sums
   int32_t i = 0;
   if constexpr (COMP) {
-    for (; i + 16 <= n; i += 16) {
-      float pa = 0.0f, pb = 0.0f;
+    for (; i + 32 <= n; i += 32) {
+      Acc p = {0.0f, 0.0f, 0.0f};
 #pragma unroll 1
-      for (int half = 0; half < 2; ++half) {
+      for (int quarter = 0; quarter < 4; ++quarter) {
         float4 sv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) sv[k] = seg[i + 8 * half + k];
+        for (int k = 0; k < 8; ++k) sv[k] = seg[i + 8 * quarter + k];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
+        for (int k = 0; k < 8; ++k) term(sv[k], p);
       }
-      kahan_add(as, ac, pa);
-      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+      add_block(p);
     }
   }
   for (; i + 8 <= n; i += 8) {
@@ -285,29 +285,35 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
     if constexpr (COMP) {
-      float pa = 0.0f, pb = 0.0f;
+      Acc p = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int k = 0; k < 8; ++k) term(sv[k], pa, pb);
-      kahan_add(as, ac, pa);
-      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+      for (int k = 0; k < 8; ++k) term(sv[k], p);
+      add_block(p);
     } else {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) term(sv[k], as, bs);
+      for (int k = 0; k < 8; ++k) term(sv[k], s_);
     }
   }
   if (i < n) {
-    float pa = 0.0f, pb = 0.0f;
-    for (; i < n; ++i) term(seg[i], pa, pb);
+    Acc p = {0.0f, 0.0f, 0.0f};
+    for (; i < n; ++i) term(seg[i], p);
     if constexpr (COMP) {
-      kahan_add(as, ac, pa);
-      if constexpr (kSpinSum) kahan_add(bs, bc, pb);
+      add_block(p);
     } else {
-      as += pa;
-      bs += pb;
+      s_.c += p.c;
+      s_.d += p.d;
+      s_.b += p.b;
     }
   }
-  A = (double)as - (double)ac;
-  B = kSpinSum ? (double)bs - (double)bc : (double)n;
+  if constexpr (!COMP) {
+    dc = s_.c;
+    dd = s_.d;
+    db = s_.b;
+  }
+  const double R = KIND == kSech2 ? (double)c.R_s : (double)c.R;
+  const double U = KIND == kSech2 ? (double)c.U_s : (double)c.U;
+  A = R * dc + U * dd;
+  B = kSpinSum ? db : (double)n;
 }
 
 // FP64 path: reads the raw FP32 unit coordinates (exact in FP64) and forms

@@ -42,6 +42,7 @@ constexpr double kLn2 = 0.69314718055994530942;
 // sech^2 FP32 path in scaled units: geometry multiplied by
 // gs = 2 log2(e)/lambda, so that r2 = (2 u log2 e)^2 (u = rho/lambda)
 constexpr double kTwoLog2e = 2.8853900817779268147;
+constexpr double kLog2e = 1.4426950408889634074;
 constexpr float kSech2ThrS = (float)(kTwoLog2e * kTwoLog2e);           // u < 1
 constexpr float kSech2Vs = (float)(1.0 / (kTwoLog2e * kTwoLog2e));     // r2 -> u^2
 constexpr float kSech2Ps = (float)(1.0 / (kLn2 * kTwoLog2e * kTwoLog2e));
@@ -57,11 +58,21 @@ __device__ __forceinline__ float horner_f32(const float (&c)[DEG + 1], float v) 
   return acc;
 }
 
+// acc * v + c as the three-address v_fma_f64.  The compiler's choice for a
+// Horner step is the two-address v_fmac_f64, whose addend register is
+// overwritten; with a loop-invariant coefficient as the addend it then
+// copies the coefficient (a 64-bit move) before every step.
+__device__ __forceinline__ double fma3_f64(double acc, double v, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(v), "v"(c));
+  return r;
+}
+
 template <int DEG>
 __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double v) {
   double acc = c[DEG];
 #pragma unroll
-  for (int k = DEG - 1; k >= 0; --k) acc = fma(acc, v, c[k]);
+  for (int k = DEG - 1; k >= 0; --k) acc = fma3_f64(acc, v, c[k]);
   return acc;
 }
 
@@ -128,29 +139,35 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
 }
 
 // ----------------------------------------------------------- FP64 fields
-// ln(1+E) for 0 <= E <= e^-1 as 2 atanh(z), z = E/(2+E) <= 0.156: the odd
-// series 2 sum z^(2k+1)/(2k+1) to 1e-17 needs 12 terms.  (The library log1p
-// evaluates in double-double and costs ~45 VGPRs.)
-__device__ __forceinline__ double log1p_small(double E) {
-  const double d = 2.0 + E;
-  double r = __builtin_amdgcn_rcp(d);
-  r = r * fma(-d, r, 2.0);
-  r = r * fma(-d, r, 2.0);
-  double z = E * r;
-  z = fma(fma(-d, z, E), r, z);  // one correction: z = E/d to ~1 ulp
-  const double z2 = z * z;
-  double p = 1.0 / 25.0;
-#pragma unroll
-  for (int k = 11; k >= 0; --k) p = fma(p, z2, 1.0 / (2 * k + 1));
-  return 2.0 * z * p;
-}
+// Elementary functions of the FP64 path, each to a few ulp (the FP64 path
+// answers to 1e-12 relative): hardware estimates refined by Newton steps,
+// and polynomials whose coefficients (wl_poly.h) sit in constant memory.
 
-// 1/x for x > 0 normal: hardware estimate and two Newton steps.
+// 1/x for x > 0 normal: the hardware estimate (about 23 correct bits) and
+// two Newton steps.
 __device__ __forceinline__ double rcp64(double x) {
   double r = __builtin_amdgcn_rcp(x);
-  r = r * fma(-x, r, 2.0);
-  r = r * fma(-x, r, 2.0);
+  r = fma(r, fma(-x, r, 1.0), r);
   return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 1/sqrt(x) for x > 0 normal: the hardware estimate and two Newton steps
+// y <- y + y (1/2 - (x/2) y^2).
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+
+// 2^-t for t >= 0: t = n + f with n = rint(t), |f| <= 1/2 (exact), a degree-11
+// polynomial for 2^-f and the exponent added by ldexp.  t is clamped at 4096
+// first (2^-4096 is 0 in FP64), so that n fits an int and f stays in range.
+__device__ __forceinline__ double exp2_neg64(double t) {
+  const double tc = fmin(t, 4096.0);
+  const double n = rint(tc);
+  const double p = horner_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, n - tc);
+  return ldexp(p, -(int)n);
 }
 
 template <int KIND>
@@ -162,9 +179,12 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
     qa = 1.0;
     qb = 1.0;
   } else if constexpr (KIND == kSech2) {
-    const double rho = sqrt(r2);
-    const double u = rho * f.inv_lam_d;
-    const double E = exp(-2.0 * u);
+    // q = 1/rho, t = 2u log2(e) with u = rho/lambda, E = exp(-2u) = 2^-t;
+    // 1/r2 = q^2.  Away from the axis (u >= 1/2, so E <= 1/e) the phase
+    // weight is (ln2 - ln(1+E) - 2u E/(1+E)) / r2 with ln(1+E) = E P(E).
+    const double q = rsq64(r2);
+    const double t = (r2 * q) * (kTwoLog2e * f.inv_lam_d);
+    const double E = exp2_neg64(t);
     const double ip = rcp64(1.0 + E);
     const double Eip = E * ip;
     qb = Eip * ip;
@@ -172,11 +192,12 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
     if (v < 0.25) {
       qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v) * f.inv_lam2_d;
     } else {
-      qa = (kLn2 - log1p_small(E) - 2.0 * u * Eip) * rcp64(r2);
+      const double L = E * horner_f64<WL_LOG1P_F64_DEG>(WL_LOG1P_F64, E);
+      qa = fma(-(t * kLn2), Eip, kLn2 - L) * (q * q);
     }
   } else if constexpr (KIND == kGauss) {
     const double v = r2 * f.inv_lam2_d;
-    const double E = exp(-v);
+    const double E = exp2_neg64(v * kLog2e);
     qb = E;
     qa = v < 0.5 ? horner_f64<WL_P_GAUSS_F64_DEG>(WL_P_GAUSS_F64, v) * f.inv_lam2_d
                  : (1.0 - E) * rcp64(r2);
@@ -327,29 +348,29 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
                                               double s, const FieldArgs& f,
                                               double& A, double& B) {
   constexpr bool kSpinSum = SPIN && KIND != kConst;
+  // cross = s^2 (m_x e_y - m_y e_x) with e the unit step and m the unit
+  // midpoint; the factor s is applied once to the sum
+  const double hs = 0.5 * s;
   double a = 0.0, b = 0.0;
-  auto step = [&](float x0f, float y0f, float x1f, float y1f) {
-    const double x0 = x0f, y0 = y0f, x1 = x1f, y1 = y1f;
-    const double mx = fma(s, 0.5 * (x0 + x1), rho);
-    const double my = s * (0.5 * (y0 + y1));
-    const double dx = s * (x1 - x0), dy = s * (y1 - y0);
-    const double cr = mx * dy - my * dx;
-    const double r2 = mx * mx + my * my;
+  auto step = [&](double x0, double y0, double x1, double y1) {
+    const double mx = fma(hs, x0 + x1, rho);
+    const double my = hs * (y0 + y1);
+    const double cr = fma(mx, y1 - y0, -(my * (x1 - x0)));  // cross / s
     double qa, qb;
-    field_f64<KIND>(r2, f, qa, qb);
+    field_f64<KIND>(fma(mx, mx, fma(my, my, 1e-300)), f, qa, qb);
     a = fma(cr, qa, a);
     if constexpr (kSpinSum) b += qb;
   };
-  float xp = X[0], yp = Y[0];
+  double xp = X[0], yp = Y[0];
   int32_t i = 1;
   for (; i < n; ++i) {
-    const float xn = X[i * stride], yn = Y[i * stride];
+    const double xn = X[i * stride], yn = Y[i * stride];
     step(xp, yp, xn, yn);
     xp = xn;
     yp = yn;
   }
   step(xp, yp, X[0], Y[0]);  // closing segment N-1 -> 0
-  A = a;
+  A = s * a;
   B = kSpinSum ? b : (double)n;
 }
 

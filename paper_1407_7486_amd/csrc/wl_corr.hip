@@ -67,11 +67,20 @@ __device__ __forceinline__ void tile_of(int32_t t, int32_t n_tiles, int32_t& bm,
 // split s of (X[k][m] - mu[m]) (X[k][n] - mu[n]), for the tiles on or above
 // the diagonal.  Wave w of the workgroup owns the 64 x 64 quarter
 // (w / 2, w % 2) of the tile: 4 x 4 MFMA blocks of 16 x 16.
+// The samples pass through LDS kBK rows at a time in two buffers: while the
+// matrix cores work on one stage, the next stage's global loads are in
+// flight into registers and land in the other buffer, so one barrier per
+// stage remains and the load latency hides behind the MFMA work.  Rows are
+// padded by kPad doubles so that the four 16-lane row groups of a wave's
+// LDS read fall on different banks.
+constexpr int kPad = 16;
+
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X,
                                               const double* __restrict__ mu, int64_t n_units,
                                               int32_t n_pts, int32_t n_tiles, int64_t k_chunk,
                                               double* __restrict__ part) {
-  __shared__ double As[kBK][kTile];
+  __shared__ double As[2][kBK][kTile + kPad];
+  __shared__ double Bs[2][kBK][kTile + kPad];
   const int32_t tid = threadIdx.x;
   const int32_t lane = tid % 64, wave = tid / 64;
   const int32_t wm = wave / 2, wn = wave % 2;
@@ -82,8 +91,6 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X,
   int64_t k_end = k_begin + k_chunk;
   if (k_end > n_units) k_end = n_units;
   const int32_t m0 = bm * kTile, n0 = bn * kTile;  // tile origin
-  const bool diag = bm == bn;
-  __shared__ double Bs[kBK][kTile];
 
   d4 acc[4][4];
 #pragma unroll
@@ -97,23 +104,50 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X,
   const int32_t m = m0 + lc, n = n0 + lc;
   const double mu_m = m < n_pts ? mu[m] : 0.0;
   const double mu_n = n < n_pts ? mu[n] : 0.0;
-  for (int64_t k0 = k_begin; k0 < k_end; k0 += kBK) {
+  // loads are unconditional, from a clamped (in-range) address, and the
+  // value is masked afterwards: a guarded load would become a branch with
+  // its own wait, serialising the stage's loads (diagonal tiles load their
+  // columns twice for the same reason)
+  const int32_t mc = m < n_pts ? m : n_pts - 1, nc = n < n_pts ? n : n_pts - 1;
+  double xa[kBK / 2], xb[kBK / 2];  // raw values of the stage in flight
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
     for (int j = 0; j < kBK / 2; ++j) {
-      const int32_t lr = lr0 + 2 * j;
-      const int64_t k = k0 + lr;
-      const bool krow = k < k_end;
-      As[lr][lc] = (krow && m < n_pts) ? X[k * n_pts + m] - mu_m : 0.0;
-      if (!diag) Bs[lr][lc] = (krow && n < n_pts) ? X[k * n_pts + n] - mu_n : 0.0;
+      const int64_t k = k0 + lr0 + 2 * j;
+      const int64_t kc = k < k_end ? k : k_end - 1;
+      xa[j] = X[kc * n_pts + mc];
+      xb[j] = X[kc * n_pts + nc];
     }
-    __syncthreads();
-    const double(*B)[kTile] = diag ? As : Bs;
+  };
+  // centring and masking happen here, after the stage's matrix work, so
+  // that nothing waits for the loads before it
+  auto stash = [&](int buf, int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < kBK / 2; ++j) {
+      const bool krow = k0 + lr0 + 2 * j < k_end;
+      As[buf][lr0 + 2 * j][lc] = (krow && m < n_pts) ? xa[j] - mu_m : 0.0;
+      Bs[buf][lr0 + 2 * j][lc] = (krow && n < n_pts) ? xb[j] - mu_n : 0.0;
+    }
+  };
+  const int32_t n_stage = (int32_t)((k_end - k_begin + kBK - 1) / kBK);
+  if (n_stage > 0) {
+    fetch(k_begin);
+    stash(0, k_begin);
+  }
+  __syncthreads();
+  for (int32_t st = 0; st < n_stage; ++st) {
+    const int32_t cur = st & 1;
+    const bool more = st + 1 < n_stage;
+    const int64_t k_next = k_begin + (int64_t)(st + 1) * kBK;
+    if (more) fetch(k_next);
+    const double(*A)[kTile + kPad] = As[cur];
+    const double(*B)[kTile + kPad] = Bs[cur];
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 4) {
       const int32_t kr = kk + lane / 16, ci = lane % 16;
       double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kr][wm * 64 + i * 16 + ci];
+      for (int i = 0; i < 4; ++i) a[i] = A[kr][wm * 64 + i * 16 + ci];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = B[kr][wn * 64 + j * 16 + ci];
 #pragma unroll
@@ -122,6 +156,9 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X,
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read in the previous stage, which every wave
+    // finished before the barrier that ended it
+    if (more) stash(cur ^ 1, k_next);
     __syncthreads();
   }
   // D block layout of the f64 16x16x4 instruction: lane l, element r ->

@@ -272,11 +272,18 @@ def main():
                                                      mode)
             dtd = time.perf_counter() - t0
             kd, nd = wl.wl_kernel_ms_total(ctx)
+            stat = de[0] > 1e-9 * np.maximum(1.0, np.abs(dm[0]))
             wl.wl_set_timing(ctx, False)
             evals = segs * seg_per_step * args.disc_steps
             disc[name] = {"kernel_ms": kd / nd, "segment_evals_per_s": evals / (kd * 1e-3),
                           "wall_s_per_call": dtd / args.disc_steps,
-                          "max_delta_over_err_N": float(np.max(dd / de[0])),
+                          # delta against the group error of <W>_N where that error is
+                          # above rounding (where W_N = 1 to rounding both are ~1e-16)
+                          "max_delta_over_err_N":
+                              float(np.max((dd / de[0])[stat])) if stat.any() else None,
+                          "frac_delta_above_err_N":
+                              float(np.mean((dd > de[0])[stat])) if stat.any() else None,
+                          "points_err_above_rounding": int(stat.sum()),
                           "finite": bool(np.isfinite(dm).all())}
             log(f"[bench] disc {name}: kernel {kd / nd:.1f} ms, "
                 f"{evals / (kd * 1e-3):.4e} seg/s")

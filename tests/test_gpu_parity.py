@@ -86,6 +86,31 @@ def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
     np.testing.assert_allclose(err, e2, rtol=1e-9, atol=1e-300)
 
 
+@pytest.mark.parametrize("lam", [0.002, 50.0])
+@pytest.mark.parametrize("pname", ["fp32c", "fp64"])
+def test_narrow_and_wide_tubes(wl, ctx, small, lam, pname):
+    """Tube widths far from the loop size: lambda = 0.002 puts the sech^2
+    exponent 2 rho/lambda beyond the FP64 exp2 clamp (E = 0) at rho = 5 and
+    the Gaussian exponent far beyond it; lambda = 50 keeps every segment on
+    the near-axis polynomials.  Per-loop values and means against the
+    oracle, spinor, all three profiles."""
+    x, y, ens = small
+    prec = PRECS[pname]
+    rho = np.array([0.0, 0.001, 0.5, 5.0])
+    T = np.geomspace(1e-4, 30.0, 9)
+    for kind in (1, 2, 3):
+        say("tube width", lam, "kind", kind, pname)
+        o = oracle.evaluate(x, y, kind, 1.3, lam, rho, T, 1, 4, per_loop=True)
+        fld = wl.field(kind, 1.3, lam)
+        ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rho, T, 1, prec, 0, 128)
+        check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1,
+                       o["phase_abs"], x.shape[1])
+        mean, _, sums = wl.wl_average(ctx, ens, fld, rho, T, 1, prec)
+        o_mean, _, _ = oracle.stats(o["group_sums"], 128)
+        check_means(prec, mean, sums, o_mean, o["group_sums"],
+                    *mean_scales(o["w"], o["spin"], 4))
+
+
 def test_subrange_and_ragged_loop_window(wl, ctx, small):
     """Per-loop evaluation of an interior window equals the matching rows of
     a full evaluation (bit for bit: the same kernel arithmetic)."""

@@ -163,7 +163,10 @@ int wl_ensemble_info(const wl_ens* ens, int64_t* n_loops, int32_t* n_ppl,
  *   group_sums [G][n_rho][n_T] sum of w over each group's loops, FP64
  * n_rho == 0 or n_T == 0 is an empty grid: WL_OK, nothing written.
  * Synchronous.  Results do not depend on the launch schedule: every group
- * sum has a single owner and a fixed summation order.
+ * sum has a single owner and a fixed summation order.  The first WL_FP64
+ * evaluation of an ensemble (here or through the batch, server, per-loop
+ * or full-loop discretisation calls) derives its FP64 segment array: 32
+ * bytes per point, freed with the ensemble.
  * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
 int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                const double* rho, int32_t n_rho, const double* T, int32_t n_T,

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -254,6 +255,33 @@ hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b) {
   return hipSuccess;
 }
 
+// FP64 segment array of the ensemble, built on first use (on `stream`, which
+// is then synchronized, so the array is complete for every stream once the
+// pointer is published).  One lock serialises the builders of all ensembles:
+// a server thread and a caller of the same ensemble may both ask.
+hipError_t ensure_seg64(const wl_ens* ens, hipStream_t stream) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (ens->d_seg64) return hipSuccess;
+  const int64_t nseg = ens->n_loops * ens->n_ppl;
+  double4* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, nseg * sizeof(double4));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hipErrorOutOfMemory;
+  }
+  e = launch_prep64(ens->d_x, ens->d_y, ens->n_loops, ens->n_ppl, d, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(d);
+    return e;
+  }
+  ens->d_seg64 = d;
+  return hipSuccess;
+}
+
+
 }  // namespace wl
 
 using namespace wl;
@@ -470,6 +498,7 @@ int wl_ensemble_free(wl_ens* ens) {
   (void)hipFree(ens->d_y);
   (void)hipFree(ens->d_seg);
   if (ens->d_sub) (void)hipFree(ens->d_sub);
+  if (ens->d_seg64) (void)hipFree(ens->d_seg64);
   delete ens;
   return WL_OK;
 }
@@ -525,12 +554,25 @@ int wl_kernel_ms_total(wl_ctx* ctx, double* total_ms, int64_t* count) {
 }
 
 
+static int need_seg64(wl_ctx* ctx, const wl_ens* ens) {
+  const hipError_t e = wl::ensure_seg64(ens, ctx->stream);
+  if (e == hipErrorOutOfMemory)
+    return fail(ctx, WL_ENOMEM, "device allocation of the FP64 segments (%lld bytes) failed",
+                (long long)(ens->n_loops * ens->n_ppl * (int64_t)sizeof(double4)));
+  if (e != hipSuccess) return hip_fail(ctx, e, "FP64 segments");
+  return WL_OK;
+}
+
 // Enqueue one evaluation; grid and outputs are device memory.
 static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
                           const double* d_rho, int32_t n_rho, const double* d_T,
                           int32_t n_T, int32_t spin, int32_t precision,
                           double* d_mean, double* d_err, double* d_sums) {
   const int32_t n_pts = n_rho * n_T;
+  if (precision == WL_FP64) {
+    int rc = need_seg64(ctx, ens);
+    if (rc) return rc;
+  }
   const wl::Sched s = make_sched(ctx, ens, n_pts);
   double* main_out = d_sums;
   if (s.n_sub > 1) {
@@ -546,9 +588,8 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
     if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
   }
   if (e == hipSuccess)
-    e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_x, ens->d_y,
-                           ens->n_ppl, d_rho, d_T, n_T, n_pts, s, main_out,
-                           ctx->stream);
+    e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_seg64, ens->n_ppl, d_rho,
+                           d_T, n_T, n_pts, s, main_out, ctx->stream);
   if (e == hipSuccess && ctx->timing) {
     e = hipEventRecord(ev1, ctx->stream);
     if (e == hipSuccess) ctx->n_timed++;
@@ -664,6 +705,7 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
       res_b += pl.back().res_bytes;
     }
     if (rq.empty()) continue;
+    if (prec == WL_FP64 && (rc = need_seg64(ctx, ens))) return rc;
     int64_t items = 0;
     for (const ReqPlan& p : pl) items += p.s.n_items;
     if (items > 0xffffffffll)
@@ -683,8 +725,8 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
     hipError_t e = hipMemcpyAsync(d_in, h_in.data(), lay.in_bytes, hipMemcpyHostToDevice,
                                   ctx->stream);
     if (e == hipSuccess)
-      e = wl::launch_batch(prec, ens->d_seg, ens->d_x, ens->d_y, ens->n_ppl, d_in,
-                           ens->n_groups, ens->n_loops, ctx->d_counter, d_res,
+      e = wl::launch_batch(prec, ens->d_seg, ens->d_seg64, ens->n_ppl, d_in, ens->n_groups,
+                           ens->n_loops, ctx->d_counter, d_res,
                            (int32_t)(want_wg < max_wg ? want_wg : max_wg), ctx->stream);
     std::vector<double> h_res((size_t)(lay.sums_n + 2 * lay.pts_n));
     if (e == hipSuccess)
@@ -728,9 +770,11 @@ static int check_subloops(wl_ctx* ctx, const wl_ens* ens) {
 }
 
 // Per-loop values of the part of each loop that `sl` names (segments of
-// `seg` for the FP32 paths, strided raw points for FP64).
+// `seg` for the FP32 paths; for FP64 the segments of `seg64` when set, for
+// whole loops, else strided raw points).
 static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
-                         const float4* seg, const wl::SubLoop& sl, const double* rho,
+                         const float4* seg, const double4* seg64, const wl::SubLoop& sl,
+                         const double* rho,
                          int32_t n_rho, const double* T, int32_t n_T, int32_t spin,
                          int32_t precision, int64_t loop0, int64_t n_loops, double* phase,
                          double* spin_exp, double* w);
@@ -749,8 +793,9 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   const wl::SubLoop sl{0, ens->n_ppl, 0, 1};
-  return per_loop_impl(ctx, ens, fa, ens->d_seg, sl, rho, n_rho, T, n_T, spin, precision,
-                       loop0, n_loops, phase, spin_exp, w);
+  if (precision == WL_FP64 && (rc = need_seg64(ctx, ens))) return rc;
+  return per_loop_impl(ctx, ens, fa, ens->d_seg, ens->d_seg64, sl, rho, n_rho, T, n_T, spin,
+                       precision, loop0, n_loops, phase, spin_exp, w);
 }
 
 int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
@@ -779,15 +824,15 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
-  return per_loop_impl(ctx, ens, fa, ens->d_sub, sl, rho, n_rho, T, n_T, spin, precision,
-                       loop0, n_loops, phase, spin_exp, w);
+  return per_loop_impl(ctx, ens, fa, ens->d_sub, nullptr, sl, rho, n_rho, T, n_T, spin,
+                       precision, loop0, n_loops, phase, spin_exp, w);
 }
 
 static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
-                         const float4* seg, const wl::SubLoop& sl, const double* rho,
-                         int32_t n_rho, const double* T, int32_t n_T, int32_t spin,
-                         int32_t precision, int64_t loop0, int64_t n_loops, double* phase,
-                         double* spin_exp, double* w) {
+                         const float4* seg, const double4* seg64, const wl::SubLoop& sl,
+                         const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                         int32_t spin, int32_t precision, int64_t loop0, int64_t n_loops,
+                         double* phase, double* spin_exp, double* w) {
   int rc;
   if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
     return fail(ctx, WL_EINVAL, "loop range [%lld, %lld) outside the ensemble",
@@ -812,7 +857,7 @@ static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = wl::launch_per_loop(precision, spin, fa, seg, ens->d_x, ens->d_y, ens->n_ppl, sl,
+    e = wl::launch_per_loop(precision, spin, fa, seg, seg64, ens->d_x, ens->d_y, ens->n_ppl, sl,
                             d_rho, d_T, n_T, (int32_t)n_pts, loop0, n_loops, d_ph, d_sp, d_w,
                             ctx->stream);
   if (e == hipSuccess && phase)
@@ -846,6 +891,7 @@ int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
+  if (precision == WL_FP64 && mode == WL_DISC_FULL && (rc = need_seg64(ctx, ens))) return rc;
   const int64_t G = ens->n_groups;
   const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
   const size_t sums_n = 4 * (size_t)G * n_pts;
@@ -877,8 +923,8 @@ int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
     if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
   }
   if (e == hipSuccess)
-    e = wl::launch_disc(precision, spin, fa, ens->d_seg, ens->d_sub, ens->d_x, ens->d_y,
-                        ens->n_ppl, d_rho, d_T, n_T, (int32_t)n_pts, s,
+    e = wl::launch_disc(precision, spin, fa, ens->d_seg, ens->d_sub, ens->d_seg64, ens->d_x,
+                        ens->d_y, ens->n_ppl, d_rho, d_T, n_T, (int32_t)n_pts, s,
                         mode == WL_DISC_FULL ? 1 : 0, level_out, ctx->stream);
   if (e == hipSuccess && ctx->timing) {
     e = hipEventRecord(ev1, ctx->stream);

@@ -46,6 +46,9 @@ struct wl_ens {
   // sub-loop segment array of the discretisation estimate, derived on first
   // use by an FP32 evaluation (same size as d_seg)
   mutable float4* d_sub = nullptr;
+  // FP64 segment array of whole loops, derived on first use by an FP64
+  // evaluation (twice the size of d_seg)
+  mutable double4* d_seg64 = nullptr;
 };
 
 namespace wl {
@@ -56,6 +59,9 @@ int check_field(wl_ctx* ctx, const wl_field* f, FieldArgs* a);
 int check_grid(wl_ctx* ctx, const double* rho, int32_t n_rho, const double* T, int32_t n_T);
 int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision);
 Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts);
+// FP64 segment array of an ensemble, built on first use on `stream`
+// (thread-safe; hipErrorOutOfMemory when the allocation fails).
+hipError_t ensure_seg64(const wl_ens* ens, hipStream_t stream);
 // Event pair for the next timed launch of ctx (pooled; created on first use).
 hipError_t next_events(wl_ctx* ctx, hipEvent_t* a, hipEvent_t* b);
 

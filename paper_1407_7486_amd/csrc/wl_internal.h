@@ -100,15 +100,21 @@ hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
 hipError_t launch_generate(uint64_t seed, int64_t first_loop, int64_t n_loops, int32_t n_ppl,
                            float* d_x, float* d_y, hipStream_t stream);
 
+// FP64 segment array (m_x, m_y^2, d_y, c per segment, 32 bytes) of every
+// loop, used by the FP64 evaluation of whole loops.
+hipError_t launch_prep64(const float* d_x, const float* d_y, int64_t n_loops,
+                         int32_t n_ppl, double4* d_seg64, hipStream_t stream);
+
+// d_seg (FP32 paths) or d_seg64 (FP64) must be set for the precision asked.
 hipError_t launch_average(int precision, int spin, const FieldArgs& f,
-                          const float4* d_seg, const float* d_x,
-                          const float* d_y, int32_t n_ppl,
+                          const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
                           const double* d_rho, const double* d_T, int32_t n_T,
                           int32_t n_pts, const Sched& s, double* d_out,
                           hipStream_t stream);
 
+// d_seg64 (may be null): the FP64 segment array, used for whole loops.
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
-                           const float4* d_seg, const float* d_x,
+                           const float4* d_seg, const double4* d_seg64, const float* d_x,
                            const float* d_y, int32_t n_ppl, const SubLoop& sl,
                            const double* d_rho, const double* d_T,
                            int32_t n_T, int32_t n_pts, int64_t loop0,
@@ -124,12 +130,13 @@ hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
 
 // Level sums for levels N, N/2, N/4: d_out [3][G*n_sub][n_pts] (with
 // n_sub == 1 these are the group sums [3][G][n_pts]).  full != 0: the N
-// level is the whole loop instead of the paper's combination of sub-loops.
+// level is the whole loop instead of the paper's combination of sub-loops
+// (for FP64 from d_seg64, which must then be set).
 hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
-                       const float4* d_sub, const float* d_x, const float* d_y,
-                       int32_t n_ppl, const double* d_rho, const double* d_T, int32_t n_T,
-                       int32_t n_pts, const Sched& s, int32_t full, double* d_out,
-                       hipStream_t stream);
+                       const float4* d_sub, const double4* d_seg64, const float* d_x,
+                       const float* d_y, int32_t n_ppl, const double* d_rho, const double* d_T,
+                       int32_t n_T, int32_t n_pts, const Sched& s, int32_t full,
+                       double* d_out, hipStream_t stream);
 
 // d_sums [4][G][n_pts] with levels 0..2 filled: writes level 3 (the
 // extrapolation), the means and errors [4][n_pts] and delta [n_pts] (each
@@ -143,10 +150,10 @@ hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
 // the descriptors).  Results at d_res: [group sums | means | errors |
 // partials] with the sizes from the header.  Grid sizes are fixed (n_wg
 // persistent workgroups), so the sequence can be captured once and replayed.
-hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
-                        const float* d_y, int32_t n_ppl, const void* d_hdr,
-                        int32_t n_groups, int64_t n_loops, unsigned int* d_counter,
-                        double* d_res, int32_t n_wg, hipStream_t stream);
+hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg64,
+                        int32_t n_ppl, const void* d_hdr, int32_t n_groups, int64_t n_loops,
+                        unsigned int* d_counter, double* d_res, int32_t n_wg,
+                        hipStream_t stream);
 
 hipError_t launch_reduce_sub(const double* d_partial, int32_t n_groups,
                              int32_t n_sub, int32_t n_pts, double* d_sums,

@@ -160,14 +160,15 @@ __device__ __forceinline__ double rsq64(double x) {
   return fma(y, fma(-h * y, y, 0.5), y);
 }
 
-// 2^-t for t >= 0: t = n + f with n = rint(t), |f| <= 1/2 (exact), a degree-11
-// polynomial for 2^-f and the exponent added by ldexp.  t is clamped at 4096
-// first (2^-4096 is 0 in FP64), so that n fits an int and f stays in range.
+// 2^-t for t >= 0: -t = n + f with n = rint(-t), |f| <= 1/2 (exact), a
+// degree-11 polynomial for 2^f and the exponent added by ldexp.  t is
+// clamped at 4096 first (2^-4096 is 0 in FP64), so that n fits an int and f
+// stays in range.
 __device__ __forceinline__ double exp2_neg64(double t) {
-  const double tc = fmin(t, 4096.0);
+  const double tc = -fmin(t, 4096.0);
   const double n = rint(tc);
-  const double p = horner_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, n - tc);
-  return ldexp(p, -(int)n);
+  const double p = horner_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, tc - n);
+  return ldexp(p, (int)n);
 }
 
 template <int KIND>
@@ -374,6 +375,34 @@ __device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
   B = kSpinSum ? b : (double)n;
 }
 
+// FP64 path over the FP64 segment array (m_x, m_y^2, d_y, c) of whole
+// loops, each entry formed once from the FP32 points (exact but for one
+// rounding of m_y^2 and c): the midpoint's radius from m_x and m_y^2, and
+// the cross product's two parts summed apart as in the FP32 path,
+// cross = s^2 c + rho s d_y.
+template <int KIND, bool SPIN>
+__device__ __forceinline__ void loop_sums_f64seg(const double4* __restrict__ seg, int32_t n,
+                                                 double rho, double s, const FieldArgs& f,
+                                                 double& A, double& B) {
+  constexpr bool kSpinSum = SPIN && KIND != kConst;
+  const double s2 = s * s;
+  double ac = 0.0, ad = 0.0, b = 0.0;
+  double4 qn = seg[0];
+  for (int32_t i = 0; i < n; ++i) {
+    // the next segment's scalar load is in flight while this one is evaluated
+    const double4 q = qn;
+    qn = seg[i + 1 < n ? i + 1 : i];
+    const double mx = fma(s, q.x, rho);
+    double qa, qb;
+    field_f64<KIND>(fma(mx, mx, fma(s2, q.y, 1e-300)), f, qa, qb);
+    ac = fma(q.w, qa, ac);
+    ad = fma(q.z, qa, ad);
+    if constexpr (kSpinSum) b += qb;
+  }
+  A = s2 * ac + (rho * s) * ad;
+  B = kSpinSum ? b : (double)n;
+}
+
 // Per-loop epilogue in FP64: phase, spin exponent and w.  The phase is
 // reduced in revolutions (cos(Phi) = cospi(2 frac(Phi/2pi))).  The FP32
 // paths take cosh from the hardware exp2 of the fractional part of
@@ -458,8 +487,7 @@ __device__ __forceinline__ int64_t remap_wg(int32_t w, int32_t n_wg, int32_t n_x
 // the sub-range's loops in order; the sum lands in out[(g*n_sub+sub)*n_pts+p].
 template <int KIND, bool SPIN, int PREC>
 __device__ __forceinline__ void run_item(
-    const float4* __restrict__ seg, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl,
+    const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, const FieldArgs& f, int64_t loops_per_group,
     int64_t loops_per_sub, int32_t n_sub, int32_t n_chunks, int64_t item,
@@ -486,7 +514,7 @@ __device__ __forceinline__ void run_item(
   for (int64_t l = l0; l < l1; ++l) {
     double A, B, phi, S;
     if constexpr (PREC == 2) {
-      loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
+      loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl, n_ppl, rho, s, f, A, B);
     } else {
       loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
     }
@@ -504,8 +532,7 @@ __device__ __forceinline__ void run_item(
 // loops_per_sub barrier iterations.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
-    const float4* __restrict__ seg, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl,
+    const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,
     double* __restrict__ out) {
@@ -538,7 +565,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
     if (l < l1) {
       double A, B, phi, S;
       if constexpr (PREC == 2) {
-        loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
+        loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl, n_ppl, rho, s, f, A, B);
       } else {
         loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
       }
@@ -559,7 +586,8 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
     const float4* __restrict__ seg, const float4* __restrict__ sub,
-    const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
+    const double4* __restrict__ seg64, const float* __restrict__ X,
+    const float* __restrict__ Y, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc, int32_t full,
     double* __restrict__ out) {
@@ -609,7 +637,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
       if (full) {
         double A, B, phi, S;
         if constexpr (PREC == 2) {
-          loop_sums_f64<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, 1, n_ppl, rho, s, f, A, B);
+          loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl, n_ppl, rho, s, f, A, B);
         } else {
           loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl, n_ppl, c, f, A, B);
         }
@@ -637,8 +665,8 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
 // index, so results do not depend on which wave ran it.
 template <int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_batch(
-    const float4* __restrict__ seg, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl, const BatchHeader* __restrict__ hdr,
+    const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
+    const BatchHeader* __restrict__ hdr,
     unsigned int* __restrict__ counter, int64_t loops_per_group) {
   const ReqDesc* __restrict__ reqs =
       (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
@@ -660,7 +688,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_batch(
     const int64_t li = item - q.item_begin;
     switch (q.f.kind * 2 + q.spin) {
 #define WL_ITEM(K, SP)                                                              \
-  run_item<K, SP, PREC>(seg, X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f,          \
+  run_item<K, SP, PREC>(seg, seg64, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f,          \
                         loops_per_group, q.loops_per_sub, q.n_sub, q.n_chunks, li, \
                         q.out)
       case 0: WL_ITEM(kConst, false); break;
@@ -751,7 +779,8 @@ __global__ void k_zero_u32(unsigned int* __restrict__ p) { *p = 0u; }
 // points x_off + k*x_stride of the raw coordinates (FP64 path).
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
-    const float4* __restrict__ seg, const float* __restrict__ X,
+    const float4* __restrict__ seg, const double4* __restrict__ seg64,
+    const float* __restrict__ X,
     const float* __restrict__ Y, int32_t n_ppl, SubLoop sl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, int32_t n_chunks, FieldArgs f, int64_t loop0,
@@ -773,8 +802,13 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   const LaneF32 c = lane_consts(rho, s, T, f);
   double A, B, phi, S;
   if constexpr (PREC == 2) {
-    loop_sums_f64<KIND, SPIN>(X + l * n_ppl + sl.x_off, Y + l * n_ppl + sl.x_off, sl.x_stride,
-                              sl.m, rho, s, f, A, B);
+    // whole loops from the FP64 segment array (the arithmetic of k_average),
+    // sub-loops from the strided points
+    if (seg64)
+      loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl, n_ppl, rho, s, f, A, B);
+    else
+      loop_sums_f64<KIND, SPIN>(X + l * n_ppl + sl.x_off, Y + l * n_ppl + sl.x_off,
+                                sl.x_stride, sl.m, rho, s, f, A, B);
   } else {
     loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl + sl.seg_off, sl.m, c, f, A, B);
   }
@@ -816,6 +850,31 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
     const float x1f = X[l * n_ppl + j], y1f = Y[l * n_ppl + j];
     if (!isfinite(x0f) || !isfinite(y0f)) *bad = 1;
     seg[t] = seg_quantities(x0f, y0f, x1f, y1f);
+  }
+}
+
+// FP64 segment array of every loop (segment i: point i -> i+1 mod N):
+// (m_x, m_y^2, d_y, c) of the FP32 points in FP64; m_x and d_y are exact,
+// m_y^2 and c rounded once.
+__global__ __launch_bounds__(256) void k_prep64(const float* __restrict__ X,
+                                                const float* __restrict__ Y,
+                                                int64_t n_loops, int32_t n_ppl,
+                                                double4* __restrict__ seg) {
+  const int64_t total = n_loops * n_ppl;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = t / n_ppl;
+    const int32_t i = (int32_t)(t % n_ppl);
+    const int32_t j = (i + 1 == n_ppl) ? 0 : i + 1;
+    const double x0 = X[l * n_ppl + i], y0 = Y[l * n_ppl + i];
+    const double x1 = X[l * n_ppl + j], y1 = Y[l * n_ppl + j];
+    const double my = 0.5 * (y0 + y1);
+    double4 o;
+    o.x = 0.5 * (x0 + x1);
+    o.y = my * my;
+    o.z = y1 - y0;
+    o.w = x0 * y1 - y0 * x1;
+    seg[t] = o;
   }
 }
 
@@ -909,34 +968,36 @@ __global__ __launch_bounds__(256) void k_disc_finish(double* __restrict__ sums,
 
 // ------------------------------------------------------------ dispatch
 template <int KIND, bool SPIN, int PREC>
-hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const float* X,
-                        const float* Y, int32_t n_ppl, const double* rho,
-                        const double* T, int32_t n_T, int32_t n_pts,
-                        const Sched& s0, double* out, hipStream_t st) {
+hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const double4* seg64,
+                        int32_t n_ppl, const double* rho, const double* T, int32_t n_T,
+                        int32_t n_pts, const Sched& s0, double* out, hipStream_t st) {
+  if (PREC == 2 ? seg64 == nullptr : seg == nullptr) return hipErrorInvalidValue;
   Sched s = s0;
   s.n_wg = (int32_t)((s.n_items + avg_waves(PREC) - 1) / avg_waves(PREC));
   hipLaunchKernelGGL((k_average<KIND, SPIN, PREC>), dim3(s.n_wg),
-                     dim3(avg_waves(PREC) * kWave), 0, st, seg, X, Y, n_ppl, rho, T,
+                     dim3(avg_waves(PREC) * kWave), 0, st, seg, seg64, n_ppl, rho, T,
                      n_T, n_pts, f, s, out);
   return hipGetLastError();
 }
 
 template <int KIND, bool SPIN, int PREC>
 hipError_t launch_disc_t(const FieldArgs& f, const float4* seg, const float4* sub,
-                         const float* X, const float* Y, int32_t n_ppl, const double* rho,
-                         const double* T, int32_t n_T, int32_t n_pts, const Sched& s0,
-                         int32_t full, double* out, hipStream_t st) {
+                         const double4* seg64, const float* X, const float* Y, int32_t n_ppl,
+                         const double* rho, const double* T, int32_t n_T, int32_t n_pts,
+                         const Sched& s0, int32_t full, double* out, hipStream_t st) {
+  if (PREC == 2 && full && seg64 == nullptr) return hipErrorInvalidValue;
   Sched s = s0;
   s.n_wg = (int32_t)((s.n_items + avg_waves(PREC) - 1) / avg_waves(PREC));
   hipLaunchKernelGGL((k_disc<KIND, SPIN, PREC>), dim3(s.n_wg),
-                     dim3(avg_waves(PREC) * kWave), 0, st, seg, sub, X, Y, n_ppl, rho, T,
-                     n_T, n_pts, f, s, full, out);
+                     dim3(avg_waves(PREC) * kWave), 0, st, seg, sub, seg64, X, Y, n_ppl, rho,
+                     T, n_T, n_pts, f, s, full, out);
   return hipGetLastError();
 }
 
 template <int KIND, bool SPIN, int PREC>
-hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const float* X,
-                       const float* Y, int32_t n_ppl, const SubLoop& sl, const double* rho,
+hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const double4* seg64,
+                       const float* X, const float* Y, int32_t n_ppl, const SubLoop& sl,
+                       const double* rho,
                        const double* T, int32_t n_T, int32_t n_pts,
                        int64_t loop0, int64_t n_loops, double* ph, double* sp,
                        double* w, hipStream_t st) {
@@ -944,8 +1005,8 @@ hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const float* X,
   const int64_t items = n_loops * n_chunks;
   const int64_t n_wg = (items + kWavesPerWG - 1) / kWavesPerWG;
   hipLaunchKernelGGL((k_per_loop<KIND, SPIN, PREC>), dim3((uint32_t)n_wg),
-                     dim3(kWavesPerWG * kWave), 0, st, seg, X, Y, n_ppl, sl, rho, T,
-                     n_T, n_pts, n_chunks, f, loop0, n_loops, ph, sp, w);
+                     dim3(kWavesPerWG * kWave), 0, st, seg, seg64, X, Y, n_ppl, sl, rho,
+                     T, n_T, n_pts, n_chunks, f, loop0, n_loops, ph, sp, w);
   return hipGetLastError();
 }
 
@@ -991,23 +1052,33 @@ hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
   return hipGetLastError();
 }
 
+hipError_t launch_prep64(const float* d_x, const float* d_y, int64_t n_loops,
+                         int32_t n_ppl, double4* d_seg64, hipStream_t stream) {
+  const int64_t total = n_loops * n_ppl;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_prep64, dim3((uint32_t)blocks), dim3(256), 0, stream, d_x, d_y,
+                     n_loops, n_ppl, d_seg64);
+  return hipGetLastError();
+}
+
 hipError_t launch_average(int precision, int spin, const FieldArgs& f,
-                          const float4* d_seg, const float* d_x,
-                          const float* d_y, int32_t n_ppl, const double* d_rho,
-                          const double* d_T, int32_t n_T, int32_t n_pts,
-                          const Sched& s, double* d_out, hipStream_t stream) {
-  WL_DISPATCH(launch_avg_t, f, d_seg, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
-              s, d_out, stream)
+                          const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
+                          const double* d_rho, const double* d_T, int32_t n_T,
+                          int32_t n_pts, const Sched& s, double* d_out, hipStream_t stream) {
+  WL_DISPATCH(launch_avg_t, f, d_seg, d_seg64, n_ppl, d_rho, d_T, n_T, n_pts, s, d_out,
+              stream)
 }
 
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
-                           const float4* d_seg, const float* d_x,
+                           const float4* d_seg, const double4* d_seg64, const float* d_x,
                            const float* d_y, int32_t n_ppl, const SubLoop& sl,
                            const double* d_rho, const double* d_T, int32_t n_T,
                            int32_t n_pts, int64_t loop0, int64_t n_loops,
                            double* d_phase, double* d_spin, double* d_w,
                            hipStream_t stream) {
-  WL_DISPATCH(launch_pl_t, f, d_seg, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
+  WL_DISPATCH(launch_pl_t, f, d_seg, d_seg64, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
               loop0, n_loops, d_phase, d_spin, d_w, stream)
 }
 
@@ -1022,12 +1093,12 @@ hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
 }
 
 hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
-                       const float4* d_sub, const float* d_x, const float* d_y,
-                       int32_t n_ppl, const double* d_rho, const double* d_T, int32_t n_T,
-                       int32_t n_pts, const Sched& s, int32_t full, double* d_out,
-                       hipStream_t stream) {
-  WL_DISPATCH(launch_disc_t, f, d_seg, d_sub, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts, s,
-              full, d_out, stream)
+                       const float4* d_sub, const double4* d_seg64, const float* d_x,
+                       const float* d_y, int32_t n_ppl, const double* d_rho, const double* d_T,
+                       int32_t n_T, int32_t n_pts, const Sched& s, int32_t full,
+                       double* d_out, hipStream_t stream) {
+  WL_DISPATCH(launch_disc_t, f, d_seg, d_sub, d_seg64, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
+              s, full, d_out, stream)
 }
 
 hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
@@ -1038,10 +1109,11 @@ hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
-                        const float* d_y, int32_t n_ppl, const void* d_hdr,
-                        int32_t n_groups, int64_t n_loops, unsigned int* d_counter,
-                        double* d_res, int32_t n_wg, hipStream_t stream) {
+hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg64,
+                        int32_t n_ppl, const void* d_hdr, int32_t n_groups, int64_t n_loops,
+                        unsigned int* d_counter, double* d_res, int32_t n_wg,
+                        hipStream_t stream) {
+  if (precision == 2 ? d_seg64 == nullptr : d_seg == nullptr) return hipErrorInvalidValue;
   const BatchHeader* hdr = (const BatchHeader*)d_hdr;
   const int64_t lpg = n_loops / n_groups;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, stream, d_counter);
@@ -1050,15 +1122,15 @@ hipError_t launch_batch(int precision, const float4* d_seg, const float* d_x,
   const dim3 blk(kWavesPerWG * kWave);
   switch (precision) {
     case 0:
-      hipLaunchKernelGGL((k_batch<0>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+      hipLaunchKernelGGL((k_batch<0>), dim3(n_wg), blk, 0, stream, d_seg, d_seg64, n_ppl,
                          hdr, d_counter, lpg);
       break;
     case 1:
-      hipLaunchKernelGGL((k_batch<1>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+      hipLaunchKernelGGL((k_batch<1>), dim3(n_wg), blk, 0, stream, d_seg, d_seg64, n_ppl,
                          hdr, d_counter, lpg);
       break;
     case 2:
-      hipLaunchKernelGGL((k_batch<2>), dim3(n_wg), blk, 0, stream, d_seg, d_x, d_y, n_ppl,
+      hipLaunchKernelGGL((k_batch<2>), dim3(n_wg), blk, 0, stream, d_seg, d_seg64, n_ppl,
                          hdr, d_counter, lpg);
       break;
     default:

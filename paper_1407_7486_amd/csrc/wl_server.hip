@@ -102,12 +102,18 @@ int32_t persistent_wgs(const wl_server* s) { return s->ctx->num_cu * 8; }
 // Captures the device work of one batch of precision `prec` on slot `sl`.
 hipError_t capture(wl_server* s, Slot* sl, int prec) {
   const wl_ens* e = s->ens;
+  if (prec == WL_FP64) {
+    // the FP64 segment array is built (once, outside the capture) before
+    // the first FP64 batch
+    const hipError_t b = wl::ensure_seg64(e, sl->stream);
+    if (b != hipSuccess) return b;
+  }
   hipError_t st = hipStreamBeginCapture(sl->stream, hipStreamCaptureModeThreadLocal);
   if (st != hipSuccess) return st;
   hipError_t r = hipMemcpyAsync(sl->d_in, sl->h_in, s->cfg.input_bytes, hipMemcpyHostToDevice,
                                 sl->stream);
   if (r == hipSuccess)
-    r = wl::launch_batch(prec, e->d_seg, e->d_x, e->d_y, e->n_ppl, sl->d_in, e->n_groups,
+    r = wl::launch_batch(prec, e->d_seg, e->d_seg64, e->n_ppl, sl->d_in, e->n_groups,
                          e->n_loops, sl->d_counter, (double*)sl->d_res, persistent_wgs(s),
                          sl->stream);
   hipGraph_t g = nullptr;

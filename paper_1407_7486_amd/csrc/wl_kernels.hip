@@ -482,6 +482,32 @@ __device__ __forceinline__ int64_t remap_wg(int32_t w, int32_t n_wg, int32_t n_x
                    : (int64_t)rem * (per + 1) + (int64_t)(xcd - rem) * per + idx;
 }
 
+// Grid point of lane index p (0 <= p < n_pts): bands of 8 rho rows,
+// enumerated T-major inside a band, so that the 64 lanes of a wave cover an
+// 8 x 8 tile of (rho, T) (for n_T a multiple of 8) rather than one rho row
+// across every T.  The loops of a tile have similar size and offset, so
+// fewer waves mix lanes whose segments pass near the axis with lanes whose
+// segments stay away from it (each lane's arithmetic is the same either
+// way).  A bijection of [0, n_pts).
+__device__ __forceinline__ int32_t tile_point(int32_t p, int32_t n_T, int32_t n_pts) {
+  constexpr int32_t kB = 8;
+  const int32_t n_rho = n_pts / n_T;
+  const int32_t band_sz = kB * n_T;
+  const int32_t full = n_rho / kB;
+  int32_t j, k;
+  if (p < full * band_sz) {
+    const int32_t band = p / band_sz, q = p - band * band_sz;
+    k = q / kB;
+    j = band * kB + (q - k * kB);
+  } else {
+    const int32_t rem = n_rho - full * kB;  // > 0: p < n_pts
+    const int32_t q = p - full * band_sz;
+    k = q / rem;
+    j = full * kB + (q - k * rem);
+  }
+  return j * n_T + k;
+}
+
 // One work item: group g, loop sub-range `sub`, grid chunk `chunk` of one
 // evaluation.  Lane j owns grid point chunk*64 + j and accumulates its w over
 // the sub-range's loops in order; the sum lands in out[(g*n_sub+sub)*n_pts+p].
@@ -504,9 +530,9 @@ __device__ __forceinline__ void run_item(
 
   const int32_t p = chunk * kWave + lane;
   const bool valid = p < n_pts;
-  const int32_t pp = valid ? p : n_pts - 1;
-  const double rho = rho_g[pp / n_T];
-  const double T = T_g[pp % n_T];
+  const int32_t pg = tile_point(valid ? p : n_pts - 1, n_T, n_pts);
+  const double rho = rho_g[pg / n_T];
+  const double T = T_g[pg % n_T];
   const double s = sqrt(T);
   const LaneF32 c = lane_consts(rho, s, T, f);
 
@@ -520,7 +546,7 @@ __device__ __forceinline__ void run_item(
     }
     acc += epilogue<SPIN, PREC>(A, B, T, n_ppl, f, phi, S);
   }
-  if (valid) out[gs * n_pts + p] = acc;
+  if (valid) out[gs * n_pts + pg] = acc;
 }
 
 // ------------------------------------------------------------- kernels
@@ -553,9 +579,9 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
 
   const int32_t p = chunk * kWave + lane;
   const bool valid = live && p < n_pts;
-  const int32_t pp = p < n_pts ? p : n_pts - 1;
-  const double rho = rho_g[pp / n_T];
-  const double T = T_g[pp % n_T];
+  const int32_t pg = tile_point(p < n_pts ? p : n_pts - 1, n_T, n_pts);
+  const double rho = rho_g[pg / n_T];
+  const double T = T_g[pg % n_T];
   const double s = sqrt(T);
   const LaneF32 c = lane_consts(rho, s, T, f);
 
@@ -573,7 +599,7 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
     }
     __syncthreads();
   }
-  if (valid) out[gs * n_pts + p] = acc;
+  if (valid) out[gs * n_pts + pg] = acc;
 }
 
 // Discretisation estimate (Sec. 4.1): the schedule, workgroup shape and
@@ -608,9 +634,9 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
 
   const int32_t p = chunk * kWave + lane;
   const bool valid = live && p < n_pts;
-  const int32_t pp = p < n_pts ? p : n_pts - 1;
-  const double rho = rho_g[pp / n_T];
-  const double T = T_g[pp % n_T];
+  const int32_t pg = tile_point(p < n_pts ? p : n_pts - 1, n_T, n_pts);
+  const double rho = rho_g[pg / n_T];
+  const double T = T_g[pg % n_T];
   const double s = sqrt(T);
   const LaneF32 c = lane_consts(rho, s, T, f);
   const int32_t h = n_ppl / 2, q = n_ppl / 4;
@@ -651,9 +677,9 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
   }
   if (valid) {
     const int64_t L = sc.n_items / sc.n_chunks;  // G * n_sub
-    out[gs * n_pts + p] = acc1;
-    out[(L + gs) * n_pts + p] = acc2;
-    out[(2 * L + gs) * n_pts + p] = acc4;
+    out[gs * n_pts + pg] = acc1;
+    out[(L + gs) * n_pts + pg] = acc2;
+    out[(2 * L + gs) * n_pts + pg] = acc4;
   }
 }
 

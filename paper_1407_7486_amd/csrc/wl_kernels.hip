@@ -43,7 +43,7 @@ constexpr double kLn2 = 0.69314718055994530942;
 // gs = 2 log2(e)/lambda, so that r2 = (2 u log2 e)^2 (u = rho/lambda)
 constexpr double kTwoLog2e = 2.8853900817779268147;
 constexpr double kLog2e = 1.4426950408889634074;
-constexpr float kSech2ThrS = (float)(kTwoLog2e * kTwoLog2e);           // u < 1
+constexpr float kSech2ThrS = (float)(0.25 * kTwoLog2e * kTwoLog2e);    // u < 1/2
 constexpr float kSech2Vs = (float)(1.0 / (kTwoLog2e * kTwoLog2e));     // r2 -> u^2
 constexpr float kSech2Ps = (float)(1.0 / (kLn2 * kTwoLog2e * kTwoLog2e));
 
@@ -99,10 +99,12 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     // = 2^-t, sech^2 u = 4 E/(1+E)^2, and since
     // u tanh u - ln cosh u = ln2 (1 - log2(1+E) - t E/(1+E)) the phase weight
     // is qa = (1 - log2(1+E) - t E/(1+E)) / r2: g/(eB0 lambda^2) divided by
-    // ln2 gs^2.  The cross product is formed in the same units (gs^2 times
-    // the unscaled one), so gs^2 cancels in the product and the FP32
-    // epilogue constant cphi32 carries ln2.  The terms cancel below u = 1,
-    // where a polynomial in u^2 is used.
+    // ln2 gs^2.  The cross product's parts are in the same units (gs^2 times
+    // the unscaled ones), so gs^2 cancels in the product and the FP32
+    // epilogue constant cphi32 carries ln2.  The terms cancel as u -> 0: below
+    // u = 1/2 a degree-4 polynomial in u^2 is used; between 1/2 and 1 the
+    // cancellation costs at most a factor ~6 (per-segment relative error
+    // below 1e-6), and fewer waves carry a near lane than with u < 1.
     const float q = __builtin_amdgcn_rsqf(r2);  // 1/t
     const float t = r2 * q;
     const float E = __builtin_amdgcn_exp2f(-t);
@@ -111,6 +113,10 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     const float Eip = E * ip;
     qb = Eip * ip;
     if (r2 < kSech2ThrS) {
+      // an empty volatile asm keeps this a branch that waves with no lane
+      // near the axis skip; as a short block the compiler would otherwise
+      // issue it for every segment
+      asm volatile("");
       const float v = r2 * kSech2Vs;
       qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * kSech2Ps;
     } else {

@@ -82,13 +82,12 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
       e2 = -2.0 * log2e / l;
       a->cphi = f->eB0 * l * l;
       a->cspin = 4.0 * f->eB0;
-      a->thr = a->lam2;  // u < 1
       break;
     case WL_GAUSS:  // g = (eB0 lam^2/2) (1-E)/rho^2, b = eB0 E
       e2 = -log2e / (l * l);
       a->cphi = 0.5 * f->eB0 * l * l;
       a->cspin = f->eB0;
-      a->thr = (float)(0.5 * l * l);  // v < 1/2
+      a->thr = (float)(0.25 * l * l);  // v < 1/4
       break;
     case WL_RATIONAL:  // g = (eB0 lam^2/2) r, b = eB0 lam^4 r^2
       a->cphi = 0.5 * f->eB0 * l * l;

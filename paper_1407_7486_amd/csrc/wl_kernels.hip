@@ -127,11 +127,13 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
-    // below v = 1/2 where 1-E cancels); b/eB0 = E.
+    // below v = 1/4, where 1-E cancels by more than a factor 4, kept as a
+    // branch that waves with no lane that close skip); b/eB0 = E.
     const float E = __builtin_amdgcn_exp2f(
         COMP ? fmaf(r2, f.exp2_scale, r2 * f.exp2_scale_lo) : r2 * f.exp2_scale);
     qb = E;
     if (r2 < f.thr) {
+      asm volatile("");
       const float v = r2 * f.inv_lam2;
       qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
     } else {

@@ -66,11 +66,9 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
   a->inv_lam_d = 1.0 / l;
   a->inv_lam2_d = 1.0 / (l * l);
   a->lam2_d = l * l;
-  a->inv_lam = (float)a->inv_lam_d;
   a->inv_lam2 = (float)a->inv_lam2_d;
   a->lam2 = (float)a->lam2_d;
   a->lam2_lo = (float)(a->lam2_d - (double)a->lam2);
-  a->two_inv_lam = (float)(2.0 / l);
   a->thr = 0.0f;
   double e2 = 0.0;
   switch (f->kind) {
@@ -79,7 +77,6 @@ int check_field(wl_ctx* ctx, const wl_field* f, wl::FieldArgs* a) {
       a->cspin = f->eB0;
       break;
     case WL_SECH2:  // g = eB0 lam^2 qa, b = eB0 * 4 * E/(1+E)^2
-      e2 = -2.0 * log2e / l;
       a->cphi = f->eB0 * l * l;
       a->cspin = 4.0 * f->eB0;
       break;

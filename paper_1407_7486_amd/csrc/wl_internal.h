@@ -33,7 +33,8 @@ struct Sched {
 // Which part of each loop a per-loop evaluation walks: m points, taken for
 // the FP32 paths as segments seg_off .. seg_off+m-1 of the loop's entries in
 // the segment array passed, for the FP64 path as points x_off + k*x_stride
-// of the raw coordinates.  Whole loop: {0, N, 0, 1} with the segment array.
+// of the raw coordinates (whole loops in FP64 read the FP64 segment array
+// instead when it is passed).  Whole loop: {0, N, 0, 1}.
 struct SubLoop {
   int32_t seg_off, m, x_off, x_stride;
 };
@@ -41,14 +42,13 @@ struct SubLoop {
 // Field constants prepared on the host for one launch.
 struct FieldArgs {
   int32_t kind;
-  // FP32 path
-  float inv_lam;     // 1/lambda
+  // FP32 path (the sech^2 one works in scaled units with constants of its
+  // own and needs none of these)
   float inv_lam2;    // 1/lambda^2
   float lam2;        // lambda^2
-  float exp2_scale;  // SECH2: -2 log2(e)/lambda ; GAUSS: -log2(e)/lambda^2
+  float exp2_scale;  // GAUSS: -log2(e)/lambda^2
   float exp2_scale_lo, lam2_lo;  // rounding residues of exp2_scale, lam2
-  float two_inv_lam;   // 2/lambda
-  float thr;           // rho^2 below which the polynomial branch is used
+  float thr;         // GAUSS: rho^2 below which the polynomial branch is used
   // FP64 path
   double inv_lam_d, inv_lam2_d, lam2_d;
   // epilogue: Phi = cphi * sum_i cross_i qa_i ; S = cspin (T/N) sum_i qb_i

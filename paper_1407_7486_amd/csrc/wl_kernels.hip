@@ -617,8 +617,14 @@ __global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_average(
 // one per level (N, N/2, N/4).  With `full`, the N level is the whole loop
 // (segment array `seg`), which doubles the segment work.  Output level k of
 // item gs lands in out[(k * G * n_sub + gs) * n_pts + p].
+// The FP32 kernels are held to 80 VGPRs (6 waves per SIMD, three 8-wave
+// workgroups per CU): their three sets of sums need ~100, which would leave
+// room for two workgroups, and the few values spilled to scratch (live
+// across the sub-loop walks, not inside them) cost less than the lost
+// occupancy.
 template <int KIND, bool SPIN, int PREC>
-__global__ __launch_bounds__(avg_waves(PREC) * kWave) void k_disc(
+__global__ __launch_bounds__(avg_waves(PREC) * kWave)
+__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 1 : 6))) void k_disc(
     const float4* __restrict__ seg, const float4* __restrict__ sub,
     const double4* __restrict__ seg64, const float* __restrict__ X,
     const float* __restrict__ Y, int32_t n_ppl,

@@ -213,6 +213,22 @@ def test_area_distribution_is_logistic():
     assert p > 1e-3
 
 
+def test_large_T_wilson_loops_follow_chebyshev_law():
+    """Scalar loops in a constant field: at large eBT the phase eBT A spreads
+    over many periods, so w = cos(phase) follows the Chebyshev (arcsine) law
+    of density 1/(pi sqrt(1 - w^2)) (Sec. 4.3); at small eBT it does not."""
+    x, y = wlinputs.dloop_ensemble(8192, 256, seed=6)
+    out = oracle.evaluate(x, y, CONST, 1.0, 1.0, np.array([0.0]), np.array([0.5, 200.0]), 0, 1,
+                          per_loop=True)
+    w = out["w"][:, 0, :]
+
+    def arcsine_cdf(v):
+        return 0.5 + np.arcsin(np.clip(v, -1.0, 1.0)) / np.pi
+
+    assert sstats.kstest(w[:, 1], arcsine_cdf).pvalue > 1e-3
+    assert sstats.kstest(w[:, 0], arcsine_cdf).pvalue < 1e-6
+
+
 # -------------------------------------------------------------- statistics
 def test_group_statistics_identities(rng):
     nl, G = 96, 8

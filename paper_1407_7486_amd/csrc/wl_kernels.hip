@@ -564,13 +564,14 @@ __device__ __forceinline__ void run_item(
 // about once per workgroup and then served from the caches.  Every wave,
 // including padding waves past the last item, runs the same
 // loops_per_sub barrier iterations.
-// The FP64 kernel is held to 128 VGPRs (4 waves per SIMD instead of 3): its
-// ~150 would otherwise fit three, and the values that no longer fit (lane
-// constants) are reloaded from scratch once per loop, outside the segment
-// walk.
+// Register budgets: the FP64 kernel is held to 128 VGPRs (4 waves per SIMD
+// instead of 3, its ~150 would fit three), the FP32 ones to 64 (8 waves,
+// four 8-wave workgroups per CU, instead of 6 at their 77).  The values
+// that no longer fit (lane constants) are reloaded from scratch once per
+// loop, outside the segment walk.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 1))) void k_average(
+__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
     const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc,

@@ -436,8 +436,14 @@ template <bool SPIN, int PREC>
 __device__ __forceinline__ double wval(double phi, double S) {
   const double rev = phi * 0.15915494309189533577;
   const double cw = cospi(2.0 * (rev - rint(rev)));
-  if constexpr (!SPIN) return cw;
-  else return cw * cosh_spin<PREC>(S);
+  if constexpr (!SPIN) {
+    return cw;
+  } else {
+    // a rounded product, never fused into a caller's sum: every kernel that
+    // adds w to a sum then gets the same bits
+#pragma clang fp contract(off)
+    return cw * cosh_spin<PREC>(S);
+  }
 }
 
 // phi = cphi A, S = cspin (T/n) B for a loop of n points, and its w.

@@ -142,6 +142,21 @@ def test_levels_small(wl, ctx, small, fname, spin, pname, mode):
 
 @pytest.mark.parametrize("spin", [0, 1])
 @pytest.mark.parametrize("pname", ["fp32c", "fp64"])
+def test_full_mode_level_n_is_the_average(wl, ctx, small, spin, pname):
+    """Full-loop mode's level N is the whole loop's w as wl_average computes
+    it: the same group sums and means, bit for bit (same kernels' segment
+    arithmetic, same loop order and sub-range split)."""
+    x, y, ens = small
+    say("full-mode level N vs average", "spin", spin, pname)
+    fld = wl.field(1, 1.3, 0.7)
+    mean, _, _, sums = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, spin, PRECS[pname], 1)
+    m1, _, s1 = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, PRECS[pname])
+    assert np.array_equal(sums[0], s1)
+    assert np.array_equal(mean[0], m1)
+
+
+@pytest.mark.parametrize("spin", [0, 1])
+@pytest.mark.parametrize("pname", ["fp32c", "fp64"])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_levels_per_loop(wl, ctx, small, spin, pname, mode):
     """One loop per group: the group sums are each loop's level values,

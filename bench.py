@@ -37,7 +37,7 @@ KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
 # WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
 # reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
 # re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": None}
+TRAFFIC = {"sech2_spinor_64k": 13678514 * 1024 * 2 + 425984 * 1024}
 
 
 def log(*a):

@@ -87,7 +87,7 @@ def _load():
         lib.wlo_loop.restype = ctypes.c_int
         lib.wlo_evaluate.argtypes = [vp, vp, i64, i32, ctypes.c_int, d, d, vp,
                                      i32, vp, i32, ctypes.c_int, ctypes.c_int,
-                                     i32, i32, vp, vp, vp, vp, vp]
+                                     i32, i32, vp, vp, vp, vp, vp, vp]
         lib.wlo_evaluate.restype = ctypes.c_int
         lib.wlo_max_threads.argtypes = []
         lib.wlo_max_threads.restype = ctypes.c_int
@@ -142,9 +142,10 @@ def evaluate(x, y, kind, eB0, lam, rho, T, spin, n_groups, nq=1,
 
     x, y: (n_loops, N) unit-loop coordinates (FP32 inputs are promoted
     exactly to FP64).  Returns a dict with ``group_sums`` of shape
-    (n_groups, n_rho, n_T) and, if ``per_loop``, ``w``, ``phase``, ``spin``
-    and ``phase_abs`` (sum of |segment phases|, the phase's conditioning) of
-    shape (n_loops, n_rho, n_T).
+    (n_groups, n_rho, n_T) and, if ``per_loop``, ``w``, ``phase``, ``spin``,
+    ``phase_abs`` (sum of |segment phases|, the phase's conditioning) and
+    ``phase_sq`` (sum of squared segment phases) of shape (n_loops, n_rho,
+    n_T).
     """
     X = np.ascontiguousarray(x, dtype=np.float64)
     Y = np.ascontiguousarray(y, dtype=np.float64)
@@ -153,22 +154,23 @@ def evaluate(x, y, kind, eB0, lam, rho, T, spin, n_groups, nq=1,
     T = np.ascontiguousarray(T, dtype=np.float64)
     nr, nt = rho.size, T.size
     gs = np.zeros((n_groups, nr, nt))
-    w = ph = sp = pa = None
+    w = ph = sp = pa = pq = None
     ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
     if per_loop:
         w = np.zeros((n_loops, nr, nt))
         ph = np.zeros((n_loops, nr, nt))
         sp = np.zeros((n_loops, nr, nt))
         pa = np.zeros((n_loops, nr, nt))
+        pq = np.zeros((n_loops, nr, nt))
     rc = _load().wlo_evaluate(X.ctypes.data, Y.ctypes.data, n_loops, n, kind,
                               eB0, lam, rho.ctypes.data, nr, T.ctypes.data, nt,
                               int(spin), nq, n_groups, n_threads,
-                              gs.ctypes.data, ptr(w), ptr(ph), ptr(sp), ptr(pa))
+                              gs.ctypes.data, ptr(w), ptr(ph), ptr(sp), ptr(pa), ptr(pq))
     if rc != 0:
         raise ValueError(f"oracle evaluate failed ({rc})")
     out = {"group_sums": gs}
     if per_loop:
-        out.update(w=w, phase=ph, spin=sp, phase_abs=pa)
+        out.update(w=w, phase=ph, spin=sp, phase_abs=pa, phase_sq=pq)
     return out
 
 

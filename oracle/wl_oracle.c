@@ -142,14 +142,15 @@ int wlo_gauss_legendre(int nq, double* t, double* w) {
 /* Phase Phi (radians) and spin exponent S of one loop at one (rho_cm, T).
  * phase_abs (may be NULL) receives sum_i |segment phase|, the size of the
  * terms the phase is summed from (its conditioning: |Phi| can be far
- * smaller when the terms cancel). */
+ * smaller when the terms cancel); phase_sq (may be NULL) sum_i (segment
+ * phase)^2, whose square root sets the rounding noise of such a sum. */
 int wlo_loop_abs(const double* yx, const double* yy, int32_t n, int kind,
                  double eB0, double lam, double rho, double T, int nq,
-                 double* phase, double* spin, double* phase_abs) {
+                 double* phase, double* spin, double* phase_abs, double* phase_sq) {
   double tq[MAX_NQ], wq[MAX_NQ];
   if (n < 2 || wlo_gauss_legendre(nq, tq, wq) != 0) return -1;
   const double s = sqrt(T);
-  double phi = 0.0, sb = 0.0, pabs = 0.0;
+  double phi = 0.0, sb = 0.0, pabs = 0.0, psq = 0.0;
   for (int32_t i = 0; i < n; ++i) {
     const int32_t j = (i + 1 == n) ? 0 : i + 1; /* closed loop */
     const double xi = rho + s * yx[i], yi = s * yy[i];
@@ -166,26 +167,28 @@ int wlo_loop_abs(const double* yx, const double* yy, int32_t n, int kind,
     }
     phi += cross * gint;
     pabs += fabs(cross * gint);
+    psq += (cross * gint) * (cross * gint);
     sb += bint;
   }
   *phase = phi;
   *spin = (T / n) * sb;
   if (phase_abs) *phase_abs = pabs;
+  if (phase_sq) *phase_sq = psq;
   return 0;
 }
 
 int wlo_loop(const double* yx, const double* yy, int32_t n, int kind,
              double eB0, double lam, double rho, double T, int nq,
              double* phase, double* spin) {
-  return wlo_loop_abs(yx, yy, n, kind, eB0, lam, rho, T, nq, phase, spin, NULL);
+  return wlo_loop_abs(yx, yy, n, kind, eB0, lam, rho, T, nq, phase, spin, NULL, NULL);
 }
 
 /*
  * Full evaluation over an ensemble.  X, Y: [n_loops][n] FP64 coordinates.
  * Grid point p = j * n_T + k  (rho[j], T[k]).
  * group_sums: [n_groups][n_rho * n_T]  (required)
- * w_out, phase_out, spin_out, phase_abs_out: [n_loops][n_rho * n_T]
- *   (each may be NULL)
+ * w_out, phase_out, spin_out, phase_abs_out, phase_sq_out:
+ *   [n_loops][n_rho * n_T] (each may be NULL)
  * Returns 0, or -1 on an invalid argument, -2 on allocation failure.
  */
 int wlo_evaluate(const double* X, const double* Y, int64_t n_loops, int32_t n,
@@ -193,7 +196,7 @@ int wlo_evaluate(const double* X, const double* Y, int64_t n_loops, int32_t n,
                  int32_t n_rho, const double* T, int32_t n_T, int spin, int nq,
                  int32_t n_groups, int32_t n_threads, double* group_sums,
                  double* w_out, double* phase_out, double* spin_out,
-                 double* phase_abs_out) {
+                 double* phase_abs_out, double* phase_sq_out) {
   if (n < 2 || n_loops < 1 || n_groups < 1 || n_loops % n_groups != 0 ||
       n_rho < 0 || n_T < 0 || nq < 1 || nq > MAX_NQ)
     return -1;
@@ -216,14 +219,15 @@ int wlo_evaluate(const double* X, const double* Y, int64_t n_loops, int32_t n,
     const double* yy = Y + l * n;
     for (int32_t a = 0; a < n_rho; ++a) {
       for (int32_t c = 0; c < n_T; ++c) {
-        double ph, S, pa;
-        wlo_loop_abs(yx, yy, n, kind, eB0, lam, rho[a], T[c], nq, &ph, &S, &pa);
+        double ph, S, pa, pq;
+        wlo_loop_abs(yx, yy, n, kind, eB0, lam, rho[a], T[c], nq, &ph, &S, &pa, &pq);
         const int64_t p = (int64_t)a * n_T + c;
         const double w = cos(ph) * (spin ? cosh(S) : 1.0);
         wbuf[l * npts + p] = w;
         if (phase_out) phase_out[l * npts + p] = ph;
         if (spin_out) spin_out[l * npts + p] = S;
         if (phase_abs_out) phase_abs_out[l * npts + p] = pa;
+        if (phase_sq_out) phase_sq_out[l * npts + p] = pq;
       }
     }
   }

@@ -120,7 +120,7 @@ def test_subloop_per_loop(wl, ctx, small, fname, spin, pname):
         m = NPPL // 2 if which == 0 else NPPL // 4
         ph, sp, w = wl.wl_subloop_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, which, 0, NL)
         check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin,
-                       o["phase_abs"], m)
+                       o["phase_sq"], o["phase_abs"])
 
 
 @pytest.mark.parametrize("fname", list(FIELDS))
@@ -177,7 +177,7 @@ def test_levels_per_loop(wl, ctx, small, spin, pname, mode):
                               per_loop=True)
     terms = subs + [full]
     ms = [NPPL // 2, NPPL // 4, NPPL // 4, NPPL]
-    lim_ph = np.max(np.stack([phase_limit(prec, t["phase"], t["phase_abs"], m)
+    lim_ph = np.max(np.stack([phase_limit(prec, t["phase"], t["phase_sq"], t["phase_abs"])
                               for t, m in zip(terms, ms)]), axis=0)
     if spin:
         s = np.max(np.abs(np.stack([t["spin"] for t in terms])), axis=0)

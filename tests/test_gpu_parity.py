@@ -74,7 +74,7 @@ def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
     fld = wl.field(kind, eB0, lam)
     ph, sp, w = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, 0, 128)
     r1 = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin,
-                        o["phase_abs"], x.shape[1])
+                        o["phase_sq"], o["phase_abs"])
     mean, err, sums = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, prec)
     o_mean, o_err, _ = oracle.stats(o["group_sums"], 128)
     r2 = check_means(prec, mean, sums, o_mean, o["group_sums"],
@@ -104,7 +104,7 @@ def test_narrow_and_wide_tubes(wl, ctx, small, lam, pname):
         fld = wl.field(kind, 1.3, lam)
         ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rho, T, 1, prec, 0, 128)
         check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1,
-                       o["phase_abs"], x.shape[1])
+                       o["phase_sq"], o["phase_abs"])
         mean, _, sums = wl.wl_average(ctx, ens, fld, rho, T, 1, prec)
         o_mean, _, _ = oracle.stats(o["group_sums"], 128)
         check_means(prec, mean, sums, o_mean, o["group_sums"],
@@ -255,7 +255,7 @@ def test_full_size_sampled(wl, ctx, big, pname):
         o = oracle.evaluate(x[l:l + 1], y[l:l + 1], cfg["kind"], cfg["eB0"], cfg["lam"],
                             rs, ts, 1, 1, per_loop=True)
         r = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1,
-                           o["phase_abs"], x.shape[1])
+                           o["phase_sq"], o["phase_abs"])
         say("loop", l, "worst error/tolerance: phase %.3g spin %.3g w %.3g" % r)
 
 
@@ -385,7 +385,7 @@ def test_maximum_size_sampled(wl, ctx):
                 o = oracle.evaluate(x[l:l + 1], y[l:l + 1], 1, 5.0, 1.0, rho, T, 1, 1,
                                     per_loop=True)
                 check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], 1,
-                               o["phase_abs"], n)
+                               o["phase_sq"], o["phase_abs"])
             per = nl // G
             for g in (0, G - 1):
                 sl = slice(g * per, (g + 1) * per)

@@ -355,3 +355,22 @@ def test_phase_conditioning_output():
                         per_loop=True)
     assert o["phase_abs"][0, 0, 0] == pytest.approx(abs(o["phase"][0, 0, 0]), rel=1e-12)
     assert o["phase_abs"][0, 1, 0] > 50 * abs(o["phase"][0, 1, 0])
+    # phase_sq = sum of squared terms: on the centred circle all n terms are
+    # equal (phase_abs / n each), and always
+    # phase_abs^2 / n <= phase_sq <= phase_abs^2 (Cauchy-Schwarz)
+    pa, pq = o["phase_abs"][0, :, 0], o["phase_sq"][0, :, 0]
+    assert pq[0] == pytest.approx(pa[0] ** 2 / n, rel=1e-12)
+    assert np.all(pa ** 2 / n <= pq * (1 + 1e-12)) and np.all(pq <= pa ** 2 * (1 + 1e-12))
+    x2, y2 = wlinputs.dloop_ensemble(4, 32, seed=5)
+    o2 = oracle.evaluate(x2, y2, SECH2, 1.0, 1.0, np.array([0.5, 3.0]), np.array([0.3, 4.0]), 0, 1,
+                         per_loop=True)
+    for l in range(4):  # brute force: the squared terms written out
+        for j, r in enumerate((0.5, 3.0)):
+            for k, T in enumerate((0.3, 4.0)):
+                s = math.sqrt(T)
+                px, py = r + s * x2[l].astype(float), s * y2[l].astype(float)
+                qx, qy = np.roll(px, -1), np.roll(py, -1)
+                mid2 = (0.5 * (px + qx)) ** 2 + (0.5 * (py + qy)) ** 2
+                g = oracle.field_g(SECH2, 1.0, 1.0, mid2)
+                t = (px * qy - py * qx) * g
+                assert o2["phase_sq"][l, j, k] == pytest.approx((t * t).sum(), rel=1e-9)

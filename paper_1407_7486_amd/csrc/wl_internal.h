@@ -84,7 +84,8 @@ struct ReqDesc {
 
 constexpr int kWavesPerWG = 4;  // batch and per-loop kernels
 // k_average: waves per workgroup (barrier-coupled), by precision; the FP64
-// kernel needs ~140 VGPRs, so smaller workgroups keep 3 waves per SIMD.
+// kernel is held to 128 VGPRs (4 waves per SIMD), so it takes workgroups of
+// 4 waves, one per SIMD.
 constexpr int avg_waves(int prec) { return prec == 2 ? 4 : 8; }
 constexpr int kWave = 64;
 

@@ -117,7 +117,6 @@ def test_subloop_per_loop(wl, ctx, small, fname, spin, pname):
     subs, _ = sub_oracle(x, y, kind, eB0, lam, spin)
     fld = wl.field(kind, eB0, lam)
     for which, o in enumerate(subs):
-        m = NPPL // 2 if which == 0 else NPPL // 4
         ph, sp, w = wl.wl_subloop_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, which, 0, NL)
         check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin,
                        o["phase_sq"], o["phase_abs"])
@@ -176,9 +175,8 @@ def test_levels_per_loop(wl, ctx, small, spin, pname, mode):
     o = oracle.discretisation(x, y, kind, eB0, lam, RHO, TGRID, spin, G, mode=mode,
                               per_loop=True)
     terms = subs + [full]
-    ms = [NPPL // 2, NPPL // 4, NPPL // 4, NPPL]
     lim_ph = np.max(np.stack([phase_limit(prec, t["phase"], t["phase_sq"], t["phase_abs"])
-                              for t, m in zip(terms, ms)]), axis=0)
+                              for t in terms]), axis=0)
     if spin:
         s = np.max(np.abs(np.stack([t["spin"] for t in terms])), axis=0)
         lim = (lim_ph + TOL[prec]["spin"] * np.maximum(1.0, s)) * np.cosh(s) * 1.01

@@ -324,7 +324,9 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
  *   delta      [n_rho][n_T]        |mean[0] - mean[3]|
  *   group_sums [4][G][n_rho][n_T]
  * The first call with WL_FP32C or WL_FP32 on an ensemble derives its
- * sub-loop segment array (16 bytes per point, freed with the ensemble).
+ * sub-loop segment array (16 bytes per point), the first with WL_FP64 its
+ * FP64 sub-loop segment array (32 bytes per point); both are freed with
+ * the ensemble.
  * Synchronous; deterministic like wl_average.  Errors: WL_EINVAL (also for
  * n_ppl not divisible by 4 or below 8), WL_ENOMEM, WL_EHIP. */
 int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,

@@ -495,6 +495,7 @@ int wl_ensemble_free(wl_ens* ens) {
   (void)hipFree(ens->d_seg);
   if (ens->d_sub) (void)hipFree(ens->d_sub);
   if (ens->d_seg64) (void)hipFree(ens->d_seg64);
+  if (ens->d_sub64) (void)hipFree(ens->d_sub64);
   delete ens;
   return WL_OK;
 }
@@ -758,6 +759,28 @@ static int ensure_sub(wl_ctx* ctx, const wl_ens* ens) {
   return WL_OK;
 }
 
+// FP64 sub-loop segment array, derived once per ensemble on the ctx stream.
+static int ensure_sub64(wl_ctx* ctx, const wl_ens* ens) {
+  if (ens->d_sub64) return WL_OK;
+  const int64_t npts = ens->n_loops * ens->n_ppl;
+  double4* d = nullptr;
+  if (hipMalloc((void**)&d, npts * sizeof(double4)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, WL_ENOMEM,
+                "device allocation of the FP64 sub-loop segments (%lld bytes) failed",
+                (long long)(npts * (int64_t)sizeof(double4)));
+  }
+  hipError_t e = wl::launch_prep_sub64(ens->d_x, ens->d_y, ens->n_loops, ens->n_ppl, d,
+                                       ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    return hip_fail(ctx, e, "FP64 sub-loop segments");
+  }
+  ens->d_sub64 = d;
+  return WL_OK;
+}
+
 static int check_subloops(wl_ctx* ctx, const wl_ens* ens) {
   if (ens->n_ppl % 4 != 0 || ens->n_ppl < 8)
     return fail(ctx, WL_EINVAL, "sub-loops need n_ppl divisible by 4 and >= 8 (have %d)",
@@ -766,8 +789,7 @@ static int check_subloops(wl_ctx* ctx, const wl_ens* ens) {
 }
 
 // Per-loop values of the part of each loop that `sl` names (segments of
-// `seg` for the FP32 paths; for FP64 the segments of `seg64` when set, for
-// whole loops, else strided raw points).
+// `seg` for the FP32 paths, of `seg64` for FP64).
 static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
                          const float4* seg, const double4* seg64, const wl::SubLoop& sl,
                          const double* rho,
@@ -788,7 +810,7 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  const wl::SubLoop sl{0, ens->n_ppl, 0, 1};
+  const wl::SubLoop sl{0, ens->n_ppl};
   if (precision == WL_FP64 && (rc = need_seg64(ctx, ens))) return rc;
   return per_loop_impl(ctx, ens, fa, ens->d_seg, ens->d_seg64, sl, rho, n_rho, T, n_T, spin,
                        precision, loop0, n_loops, phase, spin_exp, w);
@@ -809,9 +831,9 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   const int32_t h = ens->n_ppl / 2, q = ens->n_ppl / 4;
   wl::SubLoop sl;
   switch (subloop) {
-    case WL_SUB_CIRCLE: sl = wl::SubLoop{0, h, 0, 2}; break;
-    case WL_SUB_SQUARE: sl = wl::SubLoop{h, q, 1, 4}; break;
-    case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q, 3, 4}; break;
+    case WL_SUB_CIRCLE: sl = wl::SubLoop{0, h}; break;
+    case WL_SUB_SQUARE: sl = wl::SubLoop{h, q}; break;
+    case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q}; break;
     default: return fail(ctx, WL_EINVAL, "unknown sub-loop %d", subloop);
   }
   if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
@@ -819,8 +841,8 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                 (long long)loop0, (long long)(loop0 + n_loops));
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
-  return per_loop_impl(ctx, ens, fa, ens->d_sub, nullptr, sl, rho, n_rho, T, n_T, spin,
+  if ((rc = precision == WL_FP64 ? ensure_sub64(ctx, ens) : ensure_sub(ctx, ens))) return rc;
+  return per_loop_impl(ctx, ens, fa, ens->d_sub, ens->d_sub64, sl, rho, n_rho, T, n_T, spin,
                        precision, loop0, n_loops, phase, spin_exp, w);
 }
 
@@ -853,7 +875,7 @@ static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = wl::launch_per_loop(precision, spin, fa, seg, seg64, ens->d_x, ens->d_y, ens->n_ppl, sl,
+    e = wl::launch_per_loop(precision, spin, fa, seg, seg64, ens->n_ppl, sl,
                             d_rho, d_T, n_T, (int32_t)n_pts, loop0, n_loops, d_ph, d_sp, d_w,
                             ctx->stream);
   if (e == hipSuccess && phase)
@@ -886,7 +908,7 @@ int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if (n_pts == 0) return WL_OK;
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  if (precision != WL_FP64 && (rc = ensure_sub(ctx, ens))) return rc;
+  if ((rc = precision == WL_FP64 ? ensure_sub64(ctx, ens) : ensure_sub(ctx, ens))) return rc;
   if (precision == WL_FP64 && mode == WL_DISC_FULL && (rc = need_seg64(ctx, ens))) return rc;
   const int64_t G = ens->n_groups;
   const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
@@ -919,8 +941,8 @@ int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
     if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
   }
   if (e == hipSuccess)
-    e = wl::launch_disc(precision, spin, fa, ens->d_seg, ens->d_sub, ens->d_seg64, ens->d_x,
-                        ens->d_y, ens->n_ppl, d_rho, d_T, n_T, (int32_t)n_pts, s,
+    e = wl::launch_disc(precision, spin, fa, ens->d_seg, ens->d_sub, ens->d_seg64,
+                        ens->d_sub64, ens->n_ppl, d_rho, d_T, n_T, (int32_t)n_pts, s,
                         mode == WL_DISC_FULL ? 1 : 0, level_out, ctx->stream);
   if (e == hipSuccess && ctx->timing) {
     e = hipEventRecord(ev1, ctx->stream);

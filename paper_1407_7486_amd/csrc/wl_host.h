@@ -49,6 +49,9 @@ struct wl_ens {
   // FP64 segment array of whole loops, derived on first use by an FP64
   // evaluation (twice the size of d_seg)
   mutable double4* d_seg64 = nullptr;
+  // FP64 sub-loop segment array (the layout of d_sub), built on first use by
+  // an FP64 discretisation or sub-loop call
+  mutable double4* d_sub64 = nullptr;
 };
 
 namespace wl {

@@ -30,13 +30,11 @@ struct Sched {
   int32_t n_xcd;            // XCDs the dispatcher round-robins over
 };
 
-// Which part of each loop a per-loop evaluation walks: m points, taken for
-// the FP32 paths as segments seg_off .. seg_off+m-1 of the loop's entries in
-// the segment array passed, for the FP64 path as points x_off + k*x_stride
-// of the raw coordinates (whole loops in FP64 read the FP64 segment array
-// instead when it is passed).  Whole loop: {0, N, 0, 1}.
+// Which part of each loop a per-loop evaluation walks: segments seg_off ..
+// seg_off+m-1 of the loop's N entries in the segment array passed (the
+// whole-loop array, or the sub-loop one for a sub-loop).  Whole loop: {0, N}.
 struct SubLoop {
-  int32_t seg_off, m, x_off, x_stride;
+  int32_t seg_off, m;
 };
 
 // Field constants prepared on the host for one launch.
@@ -113,10 +111,11 @@ hipError_t launch_average(int precision, int spin, const FieldArgs& f,
                           int32_t n_pts, const Sched& s, double* d_out,
                           hipStream_t stream);
 
-// d_seg64 (may be null): the FP64 segment array, used for whole loops.
+// The segment array of the precision asked must be set: d_seg (FP32 paths)
+// or d_seg64 (FP64), whole-loop or sub-loop layout as `sl` says.
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
-                           const float4* d_seg, const double4* d_seg64, const float* d_x,
-                           const float* d_y, int32_t n_ppl, const SubLoop& sl,
+                           const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
+                           const SubLoop& sl,
                            const double* d_rho, const double* d_T,
                            int32_t n_T, int32_t n_pts, int64_t loop0,
                            int64_t n_loops, double* d_phase, double* d_spin,
@@ -128,14 +127,18 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
 // one (3, 7, 11, ...), in the per-segment format above.
 hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
                            int32_t n_ppl, float4* d_sub, hipStream_t stream);
+// The same sub-loop layout with the FP64 quantities of launch_prep64.
+hipError_t launch_prep_sub64(const float* d_x, const float* d_y, int64_t n_loops,
+                             int32_t n_ppl, double4* d_sub64, hipStream_t stream);
 
 // Level sums for levels N, N/2, N/4: d_out [3][G*n_sub][n_pts] (with
 // n_sub == 1 these are the group sums [3][G][n_pts]).  full != 0: the N
-// level is the whole loop instead of the paper's combination of sub-loops
-// (for FP64 from d_seg64, which must then be set).
+// level is the whole loop instead of the paper's combination of sub-loops.
+// Sub-loops come from d_sub (FP32 paths) or d_sub64 (FP64), whole loops from
+// d_seg or d_seg64; those the call uses must be set.
 hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
-                       const float4* d_sub, const double4* d_seg64, const float* d_x,
-                       const float* d_y, int32_t n_ppl, const double* d_rho, const double* d_T,
+                       const float4* d_sub, const double4* d_seg64, const double4* d_sub64,
+                       int32_t n_ppl, const double* d_rho, const double* d_T,
                        int32_t n_T, int32_t n_pts, const Sched& s, int32_t full,
                        double* d_out, hipStream_t stream);
 

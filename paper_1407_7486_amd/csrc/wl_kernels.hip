@@ -346,47 +346,10 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
   B = kSpinSum ? db : (double)n;
 }
 
-// FP64 path: reads the raw FP32 unit coordinates (exact in FP64) and forms
-// the midpoint, step and cross product of every segment in FP64.  The loop
-// is the closed polygon through X[k*stride], k = 0 .. n-1 (stride 1: the
-// whole loop; 2 or 4: an interleaved sub-loop).
-template <int KIND, bool SPIN>
-__device__ __forceinline__ void loop_sums_f64(const float* __restrict__ X,
-                                              const float* __restrict__ Y,
-                                              int32_t stride, int32_t n, double rho,
-                                              double s, const FieldArgs& f,
-                                              double& A, double& B) {
-  constexpr bool kSpinSum = SPIN && KIND != kConst;
-  // cross = s^2 (m_x e_y - m_y e_x) with e the unit step and m the unit
-  // midpoint; the factor s is applied once to the sum
-  const double hs = 0.5 * s;
-  double a = 0.0, b = 0.0;
-  auto step = [&](double x0, double y0, double x1, double y1) {
-    const double mx = fma(hs, x0 + x1, rho);
-    const double my = hs * (y0 + y1);
-    const double cr = fma(mx, y1 - y0, -(my * (x1 - x0)));  // cross / s
-    double qa, qb;
-    field_f64<KIND>(fma(mx, mx, fma(my, my, 1e-300)), f, qa, qb);
-    a = fma(cr, qa, a);
-    if constexpr (kSpinSum) b += qb;
-  };
-  double xp = X[0], yp = Y[0];
-  int32_t i = 1;
-  for (; i < n; ++i) {
-    const double xn = X[i * stride], yn = Y[i * stride];
-    step(xp, yp, xn, yn);
-    xp = xn;
-    yp = yn;
-  }
-  step(xp, yp, X[0], Y[0]);  // closing segment N-1 -> 0
-  A = s * a;
-  B = kSpinSum ? b : (double)n;
-}
-
-// FP64 path over the FP64 segment array (m_x, m_y^2, d_y, c) of whole
-// loops, each entry formed once from the FP32 points (exact but for one
-// rounding of m_y^2 and c): the midpoint's radius from m_x and m_y^2, and
-// the cross product's two parts summed apart as in the FP32 path,
+// FP64 path over an FP64 segment array (m_x, m_y^2, d_y, c) of whole loops
+// or sub-loops, each entry formed once from the FP32 points (exact but for
+// one rounding of m_y^2 and c): the midpoint's radius from m_x and m_y^2,
+// and the cross product's two parts summed apart as in the FP32 path,
 // cross = s^2 c + rho s d_y.
 template <int KIND, bool SPIN>
 __device__ __forceinline__ void loop_sums_f64seg(const double4* __restrict__ seg, int32_t n,
@@ -624,22 +587,24 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
 
 // Discretisation estimate (Sec. 4.1): the schedule, workgroup shape and
 // barrier of k_average, with the loop split into its circle, square and
-// triangle sub-loops (for FP32 from the sub-loop segment array `sub`, for
-// FP64 from the raw coordinates at stride 2 and 4) and three accumulators,
-// one per level (N, N/2, N/4).  With `full`, the N level is the whole loop
-// (segment array `seg`), which doubles the segment work.  Output level k of
-// item gs lands in out[(k * G * n_sub + gs) * n_pts + p].
+// triangle sub-loops (from the sub-loop segment array, `sub` for the FP32
+// paths, `sub64` for FP64) and three accumulators, one per level (N, N/2,
+// N/4).  With `full`, the N level is the whole loop (segment array `seg` or
+// `seg64`), which doubles the segment work.  Output level k of item gs lands
+// in out[(k * G * n_sub + gs) * n_pts + p].
 // The FP32 kernels are held to 80 VGPRs (6 waves per SIMD, three 8-wave
 // workgroups per CU): their three sets of sums need ~100, which would leave
 // room for two workgroups, and the few values spilled to scratch (live
 // across the sub-loop walks, not inside them) cost less than the lost
-// occupancy.
+// occupancy.  The FP64 kernels are held to 128 (4 waves per SIMD, as
+// k_average) for the same reason: uncapped, the sech^2 spinor one takes 178
+// (2 waves) and runs 1.46x longer per segment than k_average; capped, its
+// spills are again outside the segment walks and the two run at one rate.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 1 : 6))) void k_disc(
+__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 6))) void k_disc(
     const float4* __restrict__ seg, const float4* __restrict__ sub,
-    const double4* __restrict__ seg64, const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl,
+    const double4* __restrict__ seg64, const double4* __restrict__ sub64, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, FieldArgs f, Sched sc, int32_t full,
     double* __restrict__ out) {
@@ -673,11 +638,10 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 1 : 6))) void k_disc(
     if (l < l1) {
       double Ac, Bc, As, Bs, At, Bt;
       if constexpr (PREC == 2) {
-        const float* x = X + l * n_ppl;
-        const float* y = Y + l * n_ppl;
-        loop_sums_f64<KIND, SPIN>(x, y, 2, h, rho, s, f, Ac, Bc);
-        loop_sums_f64<KIND, SPIN>(x + 1, y + 1, 4, q, rho, s, f, As, Bs);
-        loop_sums_f64<KIND, SPIN>(x + 3, y + 3, 4, q, rho, s, f, At, Bt);
+        const double4* u = sub64 + l * n_ppl;
+        loop_sums_f64seg<KIND, SPIN>(u, h, rho, s, f, Ac, Bc);
+        loop_sums_f64seg<KIND, SPIN>(u + h, q, rho, s, f, As, Bs);
+        loop_sums_f64seg<KIND, SPIN>(u + h + q, q, rho, s, f, At, Bt);
       } else {
         const float4* u = sub + l * n_ppl;
         loop_sums_f32<KIND, SPIN, PREC == 0>(u, h, c, f, Ac, Bc);
@@ -832,13 +796,12 @@ __global__ __launch_bounds__(256) void k_stats_batch(const BatchHeader* __restri
 __global__ void k_zero_u32(unsigned int* __restrict__ p) { *p = 0u; }
 
 // Per-loop values of the (sub-)loop that takes, within each loop of the
-// ensemble, segments seg_off .. seg_off+m-1 of `seg` (FP32 paths) or the m
-// points x_off + k*x_stride of the raw coordinates (FP64 path).
+// ensemble, segments seg_off .. seg_off+m-1 of `seg` (FP32 paths) or of
+// `seg64` (FP64 path).
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
-    const float4* __restrict__ seg, const double4* __restrict__ seg64,
-    const float* __restrict__ X,
-    const float* __restrict__ Y, int32_t n_ppl, SubLoop sl,
+    const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
+    SubLoop sl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
     int32_t n_T, int32_t n_pts, int32_t n_chunks, FieldArgs f, int64_t loop0,
     int64_t n_loops, double* __restrict__ o_phase, double* __restrict__ o_spin,
@@ -859,13 +822,7 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   const LaneF32 c = lane_consts(rho, s, T, f);
   double A, B, phi, S;
   if constexpr (PREC == 2) {
-    // whole loops from the FP64 segment array (the arithmetic of k_average),
-    // sub-loops from the strided points
-    if (seg64)
-      loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl, n_ppl, rho, s, f, A, B);
-    else
-      loop_sums_f64<KIND, SPIN>(X + l * n_ppl + sl.x_off, Y + l * n_ppl + sl.x_off,
-                                sl.x_stride, sl.m, rho, s, f, A, B);
+    loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl + sl.seg_off, sl.m, rho, s, f, A, B);
   } else {
     loop_sums_f32<KIND, SPIN, PREC == 0>(seg + l * n_ppl + sl.seg_off, sl.m, c, f, A, B);
   }
@@ -910,9 +867,20 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ X,
   }
 }
 
-// FP64 segment array of every loop (segment i: point i -> i+1 mod N):
-// (m_x, m_y^2, d_y, c) of the FP32 points in FP64; m_x and d_y are exact,
-// m_y^2 and c rounded once.
+// FP64 per-segment quantities (m_x, m_y^2, d_y, c) of the segment from
+// (x0, y0) to (x1, y1): m_x and d_y exact, m_y^2 and c rounded once.
+__device__ __forceinline__ double4 seg_quantities64(double x0, double y0, double x1,
+                                                   double y1) {
+  const double my = 0.5 * (y0 + y1);
+  double4 o;
+  o.x = 0.5 * (x0 + x1);
+  o.y = my * my;
+  o.z = y1 - y0;
+  o.w = x0 * y1 - y0 * x1;
+  return o;
+}
+
+// FP64 segment array of every loop (segment i: point i -> i+1 mod N).
 __global__ __launch_bounds__(256) void k_prep64(const float* __restrict__ X,
                                                 const float* __restrict__ Y,
                                                 int64_t n_loops, int32_t n_ppl,
@@ -923,48 +891,64 @@ __global__ __launch_bounds__(256) void k_prep64(const float* __restrict__ X,
     const int64_t l = t / n_ppl;
     const int32_t i = (int32_t)(t % n_ppl);
     const int32_t j = (i + 1 == n_ppl) ? 0 : i + 1;
-    const double x0 = X[l * n_ppl + i], y0 = Y[l * n_ppl + i];
-    const double x1 = X[l * n_ppl + j], y1 = Y[l * n_ppl + j];
-    const double my = 0.5 * (y0 + y1);
-    double4 o;
-    o.x = 0.5 * (x0 + x1);
-    o.y = my * my;
-    o.z = y1 - y0;
-    o.w = x0 * y1 - y0 * x1;
-    seg[t] = o;
+    seg[t] = seg_quantities64(X[l * n_ppl + i], Y[l * n_ppl + i], X[l * n_ppl + j],
+                              Y[l * n_ppl + j]);
   }
 }
 
-// Sub-loop segment array of every loop (N divisible by 4), N entries per
-// loop: [0, N/2) the circle sub-loop (point 2j -> 2j+2), [N/2, 3N/4) the
-// square one (4j+1 -> 4j+5), [3N/4, N) the triangle one (4j+3 -> 4j+7),
-// point indices mod N.
+// Sub-loop segment layout (N divisible by 4), N entries per loop: [0, N/2)
+// the circle sub-loop (point 2j -> 2j+2), [N/2, 3N/4) the square one
+// (4j+1 -> 4j+5), [3N/4, N) the triangle one (4j+3 -> 4j+7), point indices
+// mod N.  Entry i runs from point a to point b.
+__device__ __forceinline__ void sub_endpoints(int32_t i, int32_t n_ppl, int32_t& a,
+                                              int32_t& b) {
+  const int32_t h = n_ppl / 2, q = n_ppl / 4;
+  int32_t step;
+  if (i < h) {
+    a = 2 * i;
+    step = 2;
+  } else if (i < h + q) {
+    a = 4 * (i - h) + 1;
+    step = 4;
+  } else {
+    a = 4 * (i - h - q) + 3;
+    step = 4;
+  }
+  b = a + step;
+  if (b >= n_ppl) b -= n_ppl;
+}
+
+// Sub-loop segment array of every loop, FP32 quantities.
 __global__ __launch_bounds__(256) void k_prep_sub(const float* __restrict__ X,
                                                   const float* __restrict__ Y,
                                                   int64_t n_loops, int32_t n_ppl,
                                                   float4* __restrict__ sub) {
   const int64_t total = n_loops * n_ppl;
-  const int32_t h = n_ppl / 2, q = n_ppl / 4;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = t / n_ppl;
-    const int32_t i = (int32_t)(t % n_ppl);
-    int32_t a, step;
-    if (i < h) {
-      a = 2 * i;
-      step = 2;
-    } else if (i < h + q) {
-      a = 4 * (i - h) + 1;
-      step = 4;
-    } else {
-      a = 4 * (i - h - q) + 3;
-      step = 4;
-    }
-    int32_t b = a + step;
-    if (b >= n_ppl) b -= n_ppl;
+    int32_t a, b;
+    sub_endpoints((int32_t)(t % n_ppl), n_ppl, a, b);
     const float* x = X + l * n_ppl;
     const float* y = Y + l * n_ppl;
     sub[t] = seg_quantities(x[a], y[a], x[b], y[b]);
+  }
+}
+
+// Sub-loop segment array of every loop, FP64 quantities.
+__global__ __launch_bounds__(256) void k_prep_sub64(const float* __restrict__ X,
+                                                    const float* __restrict__ Y,
+                                                    int64_t n_loops, int32_t n_ppl,
+                                                    double4* __restrict__ sub) {
+  const int64_t total = n_loops * n_ppl;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = t / n_ppl;
+    int32_t a, b;
+    sub_endpoints((int32_t)(t % n_ppl), n_ppl, a, b);
+    const float* x = X + l * n_ppl;
+    const float* y = Y + l * n_ppl;
+    sub[t] = seg_quantities64(x[a], y[a], x[b], y[b]);
   }
 }
 
@@ -1039,30 +1023,32 @@ hipError_t launch_avg_t(const FieldArgs& f, const float4* seg, const double4* se
 
 template <int KIND, bool SPIN, int PREC>
 hipError_t launch_disc_t(const FieldArgs& f, const float4* seg, const float4* sub,
-                         const double4* seg64, const float* X, const float* Y, int32_t n_ppl,
+                         const double4* seg64, const double4* sub64, int32_t n_ppl,
                          const double* rho, const double* T, int32_t n_T, int32_t n_pts,
                          const Sched& s0, int32_t full, double* out, hipStream_t st) {
-  if (PREC == 2 && full && seg64 == nullptr) return hipErrorInvalidValue;
+  if (PREC == 2 ? (sub64 == nullptr || (full && seg64 == nullptr))
+                : (sub == nullptr || (full && seg == nullptr)))
+    return hipErrorInvalidValue;
   Sched s = s0;
   s.n_wg = (int32_t)((s.n_items + avg_waves(PREC) - 1) / avg_waves(PREC));
   hipLaunchKernelGGL((k_disc<KIND, SPIN, PREC>), dim3(s.n_wg),
-                     dim3(avg_waves(PREC) * kWave), 0, st, seg, sub, seg64, X, Y, n_ppl, rho,
+                     dim3(avg_waves(PREC) * kWave), 0, st, seg, sub, seg64, sub64, n_ppl, rho,
                      T, n_T, n_pts, f, s, full, out);
   return hipGetLastError();
 }
 
 template <int KIND, bool SPIN, int PREC>
 hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const double4* seg64,
-                       const float* X, const float* Y, int32_t n_ppl, const SubLoop& sl,
-                       const double* rho,
+                       int32_t n_ppl, const SubLoop& sl, const double* rho,
                        const double* T, int32_t n_T, int32_t n_pts,
                        int64_t loop0, int64_t n_loops, double* ph, double* sp,
                        double* w, hipStream_t st) {
+  if (PREC == 2 ? seg64 == nullptr : seg == nullptr) return hipErrorInvalidValue;
   const int32_t n_chunks = (n_pts + kWave - 1) / kWave;
   const int64_t items = n_loops * n_chunks;
   const int64_t n_wg = (items + kWavesPerWG - 1) / kWavesPerWG;
   hipLaunchKernelGGL((k_per_loop<KIND, SPIN, PREC>), dim3((uint32_t)n_wg),
-                     dim3(kWavesPerWG * kWave), 0, st, seg, seg64, X, Y, n_ppl, sl, rho,
+                     dim3(kWavesPerWG * kWave), 0, st, seg, seg64, n_ppl, sl, rho,
                      T, n_T, n_pts, n_chunks, f, loop0, n_loops, ph, sp, w);
   return hipGetLastError();
 }
@@ -1129,13 +1115,13 @@ hipError_t launch_average(int precision, int spin, const FieldArgs& f,
 }
 
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
-                           const float4* d_seg, const double4* d_seg64, const float* d_x,
-                           const float* d_y, int32_t n_ppl, const SubLoop& sl,
+                           const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
+                           const SubLoop& sl,
                            const double* d_rho, const double* d_T, int32_t n_T,
                            int32_t n_pts, int64_t loop0, int64_t n_loops,
                            double* d_phase, double* d_spin, double* d_w,
                            hipStream_t stream) {
-  WL_DISPATCH(launch_pl_t, f, d_seg, d_seg64, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
+  WL_DISPATCH(launch_pl_t, f, d_seg, d_seg64, n_ppl, sl, d_rho, d_T, n_T, n_pts,
               loop0, n_loops, d_phase, d_spin, d_w, stream)
 }
 
@@ -1149,12 +1135,23 @@ hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,
   return hipGetLastError();
 }
 
+hipError_t launch_prep_sub64(const float* d_x, const float* d_y, int64_t n_loops,
+                             int32_t n_ppl, double4* d_sub64, hipStream_t stream) {
+  const int64_t total = n_loops * n_ppl;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_prep_sub64, dim3((uint32_t)blocks), dim3(256), 0, stream, d_x, d_y,
+                     n_loops, n_ppl, d_sub64);
+  return hipGetLastError();
+}
+
 hipError_t launch_disc(int precision, int spin, const FieldArgs& f, const float4* d_seg,
-                       const float4* d_sub, const double4* d_seg64, const float* d_x,
-                       const float* d_y, int32_t n_ppl, const double* d_rho, const double* d_T,
+                       const float4* d_sub, const double4* d_seg64, const double4* d_sub64,
+                       int32_t n_ppl, const double* d_rho, const double* d_T,
                        int32_t n_T, int32_t n_pts, const Sched& s, int32_t full,
                        double* d_out, hipStream_t stream) {
-  WL_DISPATCH(launch_disc_t, f, d_seg, d_sub, d_seg64, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts,
+  WL_DISPATCH(launch_disc_t, f, d_seg, d_sub, d_seg64, d_sub64, n_ppl, d_rho, d_T, n_T, n_pts,
               s, full, d_out, stream)
 }
 

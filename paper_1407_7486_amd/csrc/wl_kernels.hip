@@ -682,10 +682,14 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 6))) void k_disc(
 // The FP32 batch kernel is held to 64 VGPRs (8 waves per SIMD instead of
 // 5 at its 86): more waves hide the scalar-load and dispatch latencies of
 // the persistent item loop better than the spills it costs (measured
-// 2.20e12 -> 2.50e12 segment-evals/s on a 128-request batch).
+// 2.20e12 -> 2.50e12 segment-evals/s on a 128-request batch).  The FP64
+// one is held to 128 (4 waves per SIMD, as k_average; 2 at its 199): a batch
+// of four FP64 spinor requests (sech^2, Gaussian, rational, constant) on
+// 16384 x 4096 loops and a 64 x 64 grid took 1972 ms, now 1289 (3 waves:
+// 1440), against 1166 for the four k_average launches.
 template <int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 1 : 8))) void k_batch(
+__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_batch(
     const float4* __restrict__ seg, const double4* __restrict__ seg64, int32_t n_ppl,
     const BatchHeader* __restrict__ hdr,
     unsigned int* __restrict__ counter, int64_t loops_per_group) {

@@ -44,7 +44,7 @@ struct wl_ens {
   float* d_y = nullptr;
   float4* d_seg = nullptr;
   // sub-loop segment array of the discretisation estimate, derived on first
-  // use by an FP32 evaluation (same size as d_seg)
+  // use by an FP32 discretisation or sub-loop call (same size as d_seg)
   mutable float4* d_sub = nullptr;
   // FP64 segment array of whole loops, derived on first use by an FP64
   // evaluation (twice the size of d_seg)

@@ -174,6 +174,55 @@ def evaluate(x, y, kind, eB0, lam, rho, T, spin, n_groups, nq=1,
     return out
 
 
+# ------------------------------------- spin factor by integration by parts
+def spin_ibp_segments(yx, yy, kind, eB0, lam, rho, T, nq):
+    """Per-segment pieces of the integration-by-parts form of the spin
+    exponent (Sec. 3.2.2, Eq. Wfermfl and the equalities leading to it) for
+    one unit loop at one (rho_cm, T), with n_q-point Gauss-Legendre in t.
+
+    The scaled loop r_i = (rho_cm + s y_x,i, s y_y,i), s = sqrt(T), has
+    segments rho_i^2(t) = A_i + 2 B_i t + C_i t^2 (Sec. 3.2.1, Eqs. rhoi to
+    Ci).  With h = F f(rho^2) = rho^2 g(rho^2) (so that eB = 2 F f'(rho^2)
+    and d h/dt = eB (B_i + C_i t)), integration by parts of one segment gives
+        int_0^1 eB dt = h(1)/(B_i + C_i) - h(0)/B_i
+                        + C_i int_0^1 h / (B_i + C_i t)^2 dt
+    wherever B_i + C_i t has no zero in [0, 1].  Returns a dict of arrays
+    over the segments i (segment i runs from point i to point i+1 mod N):
+      direct    int_0^1 eB dt                     (the Eq. Wfermfpl integrand)
+      upper     h(1) / (B_i + C_i)                 (boundary term at t = 1)
+      lower     h(0) / B_i                         (boundary term at t = 0)
+      interior  C_i int_0^1 h / (B_i + C_i t)^2 dt (the Eq. Wfermfl integrand)
+      B, C      B_i, C_i
+    and the spin exponents S_direct = (T/N) sum direct (Eq. Wfermfpl) and
+    S_ibp = (T/N) sum interior (Eq. Wfermfl, which drops the boundary terms
+    on the ground that they cancel in pairs).  Plain numpy, small inputs."""
+    x = np.asarray(yx, dtype=np.float64)
+    y = np.asarray(yy, dtype=np.float64)
+    n = x.size
+    s = math.sqrt(T)
+    rx, ry = rho + s * x, s * y
+    dx, dy = np.roll(rx, -1) - rx, np.roll(ry, -1) - ry
+    A = rx * rx + ry * ry
+    B = rx * dx + ry * dy
+    C = dx * dx + dy * dy
+    t, w = np.polynomial.legendre.leggauss(nq)
+    t, w = 0.5 * (t + 1.0), 0.5 * w  # nodes and weights on [0, 1]
+    r2 = A[:, None] + 2.0 * B[:, None] * t[None, :] + C[:, None] * t[None, :] ** 2
+
+    def h(v):
+        v = np.atleast_1d(v)
+        return field_g(kind, eB0, lam, v.ravel()).reshape(v.shape) * v
+
+    eb = field_b(kind, eB0, lam, r2.ravel()).reshape(r2.shape)
+    direct = eb @ w
+    with np.errstate(divide="ignore"):
+        upper = h(A + 2.0 * B + C) / (B + C)
+        lower = h(A) / B
+    interior = C * ((h(r2) / (B[:, None] + C[:, None] * t[None, :]) ** 2) @ w)
+    return dict(direct=direct, upper=upper, lower=lower, interior=interior, B=B, C=C,
+                S_direct=T / n * direct.sum(), S_ibp=T / n * interior.sum())
+
+
 # ------------------------------------------------------------ statistics
 def stats(group_sums, n_loops):
     """Mean, group standard error and delete-a-group jackknife error.

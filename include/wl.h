@@ -185,6 +185,32 @@ int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                      int32_t n_T, int32_t spin, int32_t precision,
                      double* d_mean, double* d_err, double* d_group_sums);
 
+/* Largest device scratch the allocation-free evaluation can use. */
+#define WL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* As wl_average_async, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * wl_average_async; the call allocates nothing (no hipMalloc / hipFree, no
+ * event creation) and records no kernel timing.  Its only scratch, the
+ * sub-range partial sums G * n_sub * n_rho * n_T * 8 bytes (n_sub the
+ * library's split of each group's loops, at most 64, 1 when a group is
+ * small or the grid large), lives in a static device array of
+ * WL_NOALLOC_SCRATCH_BYTES per device, reserved when the library is loaded
+ * and held until the process ends.  Every call on a device shares that
+ * array: calls that overlap on one device (two contexts or streams)
+ * race and must be serialised by the caller.  Nothing in the array needs
+ * to start at zero.
+ * Errors: WL_EINVAL as wl_average_async, and also when the partial sums
+ * would exceed WL_NOALLOC_SCRATCH_BYTES (message gives both sizes) or when
+ * precision is WL_FP64 and the ensemble's FP64 segment array does not exist
+ * yet (an FP64 wl_average or wl_average_async derives it); WL_EHIP when the
+ * scratch array's device address could not be obtained at wl_create. */
+int wl_average_async_noalloc(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                             const double* d_rho, int32_t n_rho, const double* d_T,
+                             int32_t n_T, int32_t spin, int32_t precision,
+                             double* d_mean, double* d_err, double* d_group_sums);
+
 /* One request of a batched evaluation (host memory, caller-owned).  The
  * outputs have the shapes of wl_average's and may each be NULL. */
 typedef struct wl_request {

@@ -25,6 +25,7 @@ WL_FP32C, WL_FP32, WL_FP64 = 0, 1, 2
 WL_HOST_PTR, WL_DEVICE_PTR = 0, 1
 WL_DISC_PAPER, WL_DISC_FULL = 0, 1
 WL_SUB_CIRCLE, WL_SUB_SQUARE, WL_SUB_TRIANGLE = 0, 1, 2
+WL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every entry point declared in include/wl.h
 EXPORTS = (
@@ -36,7 +37,7 @@ EXPORTS = (
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
     "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
     "wl_ensemble_generate", "wl_ensemble_download", "wl_ensemble_set_groups",
-    "wl_correlation", "wl_regroup",
+    "wl_correlation", "wl_regroup", "wl_average_async_noalloc",
 )
 
 
@@ -110,6 +111,8 @@ _sigs = {
                     _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "wl_average_async": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp,
                           _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "wl_average_async_noalloc": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp,
+                                  _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "wl_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
                      _i32, _i32, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "wl_discretisation": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
@@ -360,6 +363,16 @@ def wl_average_async(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,
                                  d_rho.numel(), _ptr(d_T), d_T.numel(),
                                  int(spin), int(precision), _ptr(d_mean),
                                  _ptr(d_err), _ptr(d_group_sums)), ctx)
+
+
+def wl_average_async_noalloc(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,
+                             d_err, d_group_sums):
+    """As wl_average_async, through the allocation-free entry point (partial
+    sums in the library's static device scratch)."""
+    _check(_lib.wl_average_async_noalloc(ctx, ens, ctypes.byref(fld), _ptr(d_rho),
+                                         d_rho.numel(), _ptr(d_T), d_T.numel(),
+                                         int(spin), int(precision), _ptr(d_mean),
+                                         _ptr(d_err), _ptr(d_group_sums)), ctx)
 
 
 def wl_average_batch(ctx, ens, requests):

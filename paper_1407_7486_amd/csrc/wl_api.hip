@@ -278,6 +278,39 @@ hipError_t ensure_seg64(const wl_ens* ens, hipStream_t stream) {
 }
 
 
+// Scratch of the allocation-free evaluation (wl_average_async_noalloc):
+// one copy per device, reserved when the code object is loaded on it and
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address is obtained once
+// per device with hipGetSymbolAddress (noalloc_scratch_ptr) and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[WL_NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, looked up on the
+// first call for each device and kept.
+static hipError_t noalloc_scratch_ptr(int device, void** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDev] = {};
+  static hipError_t status[kMaxDev] = {};
+  static bool done[kMaxDev] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done[device]) {
+    void* p = nullptr;
+    status[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (status[device] != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    ptr[device] = p;
+    done[device] = true;
+  }
+  *out = ptr[device];
+  return status[device];
+}
+
 }  // namespace wl
 
 using namespace wl;
@@ -322,6 +355,10 @@ int wl_create(wl_ctx** out, int device, void* hip_stream) {
     wl_destroy(c);
     return WL_ENOMEM;
   }
+  // with the context's device current: the allocation-free entry point's
+  // scratch address on this device (a failure is reported by that entry
+  // point only)
+  c->noalloc_status = noalloc_scratch_ptr(device, &c->d_noalloc);
   *out = c;
   return WL_OK;
 }
@@ -560,34 +597,53 @@ static int need_seg64(wl_ctx* ctx, const wl_ens* ens) {
   return WL_OK;
 }
 
-// Enqueue one evaluation; grid and outputs are device memory.
+// Enqueue one evaluation; grid and outputs are device memory.  With
+// `noalloc` the call allocates nothing: the partial sums go to the static
+// scratch array (ctx->d_noalloc), the FP64 segment array must exist
+// already, and no timing events are recorded.
 static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
                           const double* d_rho, int32_t n_rho, const double* d_T,
                           int32_t n_T, int32_t spin, int32_t precision,
-                          double* d_mean, double* d_err, double* d_sums) {
+                          double* d_mean, double* d_err, double* d_sums,
+                          bool noalloc = false) {
   const int32_t n_pts = n_rho * n_T;
   if (precision == WL_FP64) {
-    int rc = need_seg64(ctx, ens);
-    if (rc) return rc;
+    if (noalloc) {
+      if (!ens->d_seg64)
+        return fail(ctx, WL_EINVAL,
+                    "the ensemble's FP64 segment array does not exist yet (an FP64 "
+                    "wl_average or wl_average_async derives it)");
+    } else {
+      int rc = need_seg64(ctx, ens);
+      if (rc) return rc;
+    }
   }
   const wl::Sched s = make_sched(ctx, ens, n_pts);
   double* main_out = d_sums;
   if (s.n_sub > 1) {
     const size_t need = (size_t)ens->n_groups * s.n_sub * n_pts * sizeof(double);
-    int rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "partial sums");
-    if (rc) return rc;
-    main_out = (double*)ctx->d_partial;
+    if (noalloc) {
+      if (need > WL_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, WL_EINVAL,
+                    "partial sums need %zu bytes, above the %zu-byte scratch of the "
+                    "allocation-free evaluation", need, (size_t)WL_NOALLOC_SCRATCH_BYTES);
+      main_out = (double*)ctx->d_noalloc;
+    } else {
+      int rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "partial sums");
+      if (rc) return rc;
+      main_out = (double*)ctx->d_partial;
+    }
   }
   hipError_t e = hipSuccess;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (ctx->timing) {
+  if (ctx->timing && !noalloc) {
     e = next_events(ctx, &ev0, &ev1);
     if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
   }
   if (e == hipSuccess)
     e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_seg64, ens->n_ppl, d_rho,
                            d_T, n_T, n_pts, s, main_out, ctx->stream);
-  if (e == hipSuccess && ctx->timing) {
+  if (e == hipSuccess && ctx->timing && !noalloc) {
     e = hipEventRecord(ev1, ctx->stream);
     if (e == hipSuccess) ctx->n_timed++;
   }
@@ -600,10 +656,11 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
   return WL_OK;
 }
 
-int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
-                     const double* d_rho, int32_t n_rho, const double* d_T,
-                     int32_t n_T, int32_t spin, int32_t precision,
-                     double* d_mean, double* d_err, double* d_group_sums) {
+static int average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                         const double* d_rho, int32_t n_rho, const double* d_T,
+                         int32_t n_T, int32_t spin, int32_t precision,
+                         double* d_mean, double* d_err, double* d_group_sums,
+                         bool noalloc) {
   if (!ctx) return WL_EINVAL;
   ctx->err.clear();
   int rc = check_common(ctx, ens, spin, precision);
@@ -616,10 +673,28 @@ int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if ((int64_t)n_rho * n_T == 0) return WL_OK;
   if (!d_rho || !d_T || !d_group_sums)
     return fail(ctx, WL_EINVAL, "device pointer is NULL");
+  if (noalloc && !ctx->d_noalloc)
+    return hip_fail(ctx, ctx->noalloc_status, "address of the allocation-free scratch");
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   return average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
-                        d_err, d_group_sums);
+                        d_err, d_group_sums, noalloc);
+}
+
+int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                     const double* d_rho, int32_t n_rho, const double* d_T,
+                     int32_t n_T, int32_t spin, int32_t precision,
+                     double* d_mean, double* d_err, double* d_group_sums) {
+  return average_async(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
+                       d_err, d_group_sums, false);
+}
+
+int wl_average_async_noalloc(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                             const double* d_rho, int32_t n_rho, const double* d_T,
+                             int32_t n_T, int32_t spin, int32_t precision,
+                             double* d_mean, double* d_err, double* d_group_sums) {
+  return average_async(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
+                       d_err, d_group_sums, true);
 }
 
 int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,

@@ -28,6 +28,11 @@ struct wl_ctx {
   void* d_batch = nullptr;  // batched evaluation: descriptors, grids, results
   size_t batch_bytes = 0;
   unsigned int* d_counter = nullptr;  // work counter of persistent launches
+  // device address of the allocation-free entry point's static scratch
+  // array on this context's device (nullptr if it could not be obtained;
+  // noalloc_status then holds the HIP error)
+  void* d_noalloc = nullptr;
+  hipError_t noalloc_status = hipSuccess;
   // timing of the main kernel: one event pair per launch since timing was
   // enabled (pairs are pooled and reused)
   bool timing = false;

@@ -59,8 +59,8 @@ def test_null_arguments_are_rejected_without_a_device(wl):
     assert lib.wl_ensemble_free(None) == wl.WL_OK
     lib.wl_ensemble_info.argtypes = [ctypes.c_void_p] * 4
     assert lib.wl_ensemble_info(None, None, None, None) == wl.WL_EINVAL
-    for fn in ("wl_average", "wl_average_async", "wl_per_loop",
-               "wl_ensemble_upload"):
+    for fn in ("wl_average", "wl_average_async", "wl_average_async_noalloc",
+               "wl_per_loop", "wl_ensemble_upload"):
         f = getattr(lib, fn)
         f.restype = ctypes.c_int
         # a NULL context is rejected before anything else is read
@@ -82,6 +82,13 @@ def test_null_arguments_are_rejected_without_a_device(wl):
     assert lib.wl_set_timing(None, 1) == wl.WL_EINVAL
     lib.wl_last_kernel_ms.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert lib.wl_last_kernel_ms(None, None) == wl.WL_EINVAL
+
+
+def test_noalloc_scratch_size_matches_the_header(wl):
+    txt = open(HEADER).read()
+    m = re.search(r"#define WL_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m, "WL_NOALLOC_SCRATCH_BYTES not found"
+    assert wl.WL_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
 
 
 def test_no_device_is_reported_cleanly(wl):

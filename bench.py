@@ -2,8 +2,10 @@
 
 One step = one full evaluation of the workload's (rho_cm, T) grid over the
 device-resident loop ensemble: the main kernel (segment sums, per-loop
-epilogue, group accumulation), the sub-range reduction and the group
-statistics.  The ensemble is uploaded before timing.  Prints one JSON line.
+epilogue, group accumulation, scale and rounding accumulators), the
+per-point scale and rounding estimate with the FP64 recomputation of the
+points it flags, the sub-range reduction and the group statistics.  The
+ensemble is uploaded before timing.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -18,30 +20,79 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loop-segment evals/s (N_l*N_ppl*N_rho*N_T) FP32c vs FP64; serve p50/p99 ms"
 
-# Algorithmic VALU cost of one segment evaluation in the FP32 compensated
-# kernel, in FP32 lane-op slots: every VALU instruction of the formulation
-# (multiply-adds fused) counts 1 and every transcendental (exp, log, rcp,
-# rsq) counts 4 (measured on MI355X: a transcendental costs ~4 FMA issue
-# slots).  The sech^2 spinor count is the far-from-axis branch: 14
-# instructions + 4 transcendentals, plus the FP64 accumulation of the
-# 32-segment block sums amortised (a conversion and an add per block and
-# sum: 3 x 2 / 32).
-SLOTS_FP32C = {("sech2", 1): 30.1875, ("sech2", 0): 29.125, ("gauss", 1): 20.1875,
-               ("gauss", 0): 19.125, ("rational", 1): 13.1875, ("rational", 0): 12.125,
-               ("const", 1): 2.125, ("const", 0): 2.125}
-# FP32 VALU peak: 157.3 TFLOP/s / 2 flop per FMA = 256 CUs x 128 FP32
-# lanes/clk x 2.4 GHz lane-ops per second.
-PEAK_OPS = 256 * 128 * 2.4e9
+# Algorithmic work of one segment evaluation, in FP32 slot-equivalents of
+# the minimal midpoint formulation: every VALU operation counts 1, every
+# transcendental (exp, log, rcp, rsq) 4.  About 19 operations are common to
+# every field (scale and shift, step, cross product, midpoint radius,
+# product, and two compensated updates, of which the scalar path needs one,
+# 4 fewer); sech^2 adds 14 operations and 4 transcendentals (rsq, exp, rcp,
+# log; exp(-2u) shared by tanh, ln cosh and sech^2), the Gaussian 6 and 2,
+# the rational profile 5 and 1, the constant field nothing.  sech^2 spinor:
+# 19 + 14 + 16 = 49.
+SLOTS = {("sech2", 1): 49.0, ("sech2", 0): 45.0, ("gauss", 1): 33.0, ("gauss", 0): 29.0,
+         ("rational", 1): 28.0, ("rational", 0): 24.0, ("const", 1): 19.0,
+         ("const", 0): 15.0}
+# Published FP32 vector peak of the MI355X (256 CUs, 2.4 GHz).
+PEAK_FP32 = 157.3e12
 KIND_NAMES = {0: "const", 1: "sech2", 2: "gauss", 3: "rational"}
-# HBM bytes per launch of the main kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, each scaled by its reading for a plain 1 GiB copy (FETCH_SIZE
-# reads 0.5 GiB there: factor 2; WRITE_SIZE reads 1 GiB: factor 1).  Must be
-# re-measured whenever the kernel changes; None when stale.
-TRAFFIC = {"sech2_spinor_64k": 13678514 * 1024 * 2 + 425984 * 1024}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_1407_7486_amd", "csrc", "wl_kernels.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(workload):
+    """HBM bytes per launch of the main kernel from the committed profile
+    summary profiles/k_average_<workload>.md: its line
+      traffic: fetch_kib=F write_kib=W fetch_factor=a write_factor=b source=H
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by its
+    reading for a plain copy of known size).  None when the summary's kernel
+    source hash H is not that of the kernels built now (stale counters)."""
+    import re
+    path = os.path.join(PROFILES, f"k_average_{workload}.md")
+    if not os.path.exists(path):
+        return None, None
+    m = re.search(r"traffic: fetch_kib=([\d.]+) write_kib=([\d.]+) fetch_factor=([\d.]+) "
+                  r"write_factor=([\d.]+) source=([0-9a-f]+)", open(path).read())
+    if not m:
+        return None, None
+    f, w, a, b, h = m.groups()
+    if h != kernel_source_hash():
+        return None, h
+    return (float(f) * float(a) + float(w) * float(b)) * 1024, h
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def valu_rates():
+    """VALU issue rates of the chip from the probe library (FP32 FMA,
+    transcendental, FP64 FMA wave-instructions per second over all CUs)."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1407_7486_amd", "libwl_probe.so"))
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rates = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * 3)()
+    rc = lib.wl_probe_valu_rates(ctypes.c_int(n_cu), ctypes.c_int(3), rates, ms)
+    if rc != 0:
+        raise RuntimeError(f"VALU probe failed with HIP error {rc}")
+    clock = 2.4e9
+    simds = 4 * n_cu
+    out = {"n_cu": n_cu, "fp32_fma_wave_insts_per_s": rates[0],
+           "trans_wave_insts_per_s": rates[1], "fp64_fma_wave_insts_per_s": rates[2],
+           "ms": list(ms),
+           # cycles per wave-instruction per SIMD at the 2.4 GHz peak clock
+           "cycles_per_inst_at_2.4GHz": [simds * clock / r for r in rates],
+           "fp32_fma_lane_ops_per_s": 64 * rates[0]}
+    print(json.dumps(out), flush=True)
+    print(f"rates: fp32={rates[0]:.6e} trans={rates[1]:.6e} fp64={rates[2]:.6e}", flush=True)
 
 
 def copy_calibration(nbytes):
@@ -60,23 +111,26 @@ def copy_calibration(nbytes):
                       "GBps_read_plus_write": 2 * 4 * n / dt / 1e9}), flush=True)
 
 
-def serve_run(wl, ctx, args):
-    """Bounded serving run: Poisson arrivals of uneven requests (sech^2 or
-    Gaussian tube, eB0 ~ U[0.5,10], lambda ~ U[0.2,5], N_rho ~ U{4..128},
-    N_T ~ U{8..64}, spin 50/50, FP32C; request seed 1) against a resident
-    ensemble of 4096-point loops; latency = completion - arrival."""
+def serve_run(wl, ctx, rate, n_requests, nl):
+    """Bounded serving run: Poisson arrivals at `rate` per second of
+    n_requests uneven requests (sech^2 or Gaussian tube, eB0 ~ U[0.5,10],
+    lambda ~ U[0.2,5], N_rho ~ U{4..128}, N_T ~ U{8..64}, spin 50/50, FP32C;
+    request seed 1) against a resident ensemble of nl loops of 4096 points;
+    latency = completion - arrival.  Below capacity the latencies are the
+    requests' service times (batching included); above it they include the
+    queueing behind earlier requests."""
     import numpy as np
 
     import wlinputs
-    nl, n_ppl = args.serve_loops, 4096
+    n_ppl = 4096
     x, y = wlinputs.dloop_ensemble(nl, n_ppl, seed=0)
     ens = wl.wl_ensemble_upload(ctx, x, y, 64)
     del x, y
-    reqs = wlinputs.draw_requests(args.serve_requests, seed=1)
+    reqs = wlinputs.draw_requests(n_requests, seed=1)
     rng = np.random.Generator(np.random.Philox(key=2))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
     srv = wl.Server(ctx, ens, slots=2)
-    log(f"[bench] serve: {len(reqs)} requests at {args.serve_rate}/s on {nl} loops")
+    log(f"[bench] serve: {len(reqs)} requests at {rate}/s on {nl} loops")
     t0 = time.perf_counter()
     tickets = []
     for q, ta in zip(reqs, arrivals):
@@ -85,27 +139,98 @@ def serve_run(wl, ctx, args):
             time.sleep(ta - now)
         q["precision"] = wl.WL_FP32C
         tickets.append((srv.submit(q), time.perf_counter() - t0))
-    lat = []
+    lat, esc = [], 0
     for t, ts in tickets:
         st, ms = srv.wait(t, 600.0)
         if st != 0:
             raise RuntimeError(f"serving request failed with status {st}")
         lat.append(ms)
-        srv.result(t)
+        esc += int(srv.result(t, full=True)["escalated"].sum())
     t_end = time.perf_counter() - t0
     info = srv.info()
     srv.close()
     wl.wl_ensemble_free(ens)
-    segs = sum(q["rho"].size * q["T"].size for q in reqs) * nl * n_ppl
+    pts = sum(q["rho"].size * q["T"].size for q in reqs)
+    segs = pts * nl * n_ppl
     lat = np.array(lat)
-    out = {"requests": len(reqs), "offered_rate": args.serve_rate,
+    out = {"requests": len(reqs), "offered_rate": rate,
            "achieved_rate": len(reqs) / t_end, "n_loops": nl, "n_ppl": n_ppl,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "segment_evals_per_s": segs / t_end, "wall_s": t_end,
-           "batches": info["batches"], "slots": 2}
-    log(f"[bench] serve p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms, "
+           "batches": info["batches"], "slots": 2, "escalated_fraction": esc / pts}
+    log(f"[bench] serve at {rate}/s: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms, "
         f"{out['segment_evals_per_s']:.3e} seg/s, {info['batches']} batches")
     return out
+
+
+def c3_run(wl, ctx, torch, dev, precision_report):
+    """The precision-stress configuration at its full size: 131072 d-loops of
+    8192 points (generated on the device from the seed-0 stream), sech^2 tube
+    eB0 = 20, lambda = 4, 32 rho_cm in [0, 5], 48 T in [1e-3, 10] (eB0 T up
+    to 200), spinor: one timed compensated-FP32 and one FP64 evaluation."""
+    import numpy as np
+
+    import wlinputs
+    nl, n_ppl, G = 131072, 8192, 64
+    rho = wlinputs.rho_grid(0.0, 5.0, 32)
+    T = wlinputs.t_grid(1e-3, 200.0 / 20.0, 48)
+    segs = nl * n_ppl * rho.size * T.size
+    ens = wl.wl_ensemble_generate(ctx, 0, 0, nl, n_ppl, G)
+    fld = wl.field(wl.WL_SECH2, 20.0, 4.0)
+    d_rho = torch.tensor(rho, dtype=torch.float64, device=dev)
+    d_T = torch.tensor(T, dtype=torch.float64, device=dev)
+    outs = {"mean": torch.empty((rho.size, T.size), dtype=torch.float64, device=dev),
+            "group_sums": torch.empty((G, rho.size, T.size), dtype=torch.float64, device=dev),
+            "scale": torch.empty((rho.size, T.size), dtype=torch.float64, device=dev),
+            "fp_err": torch.empty((rho.size, T.size), dtype=torch.float64, device=dev),
+            "escalated": torch.empty((rho.size, T.size), dtype=torch.uint8, device=dev)}
+    res = {}
+    for prec, name in ((wl.WL_FP32C, "fp32c"), (wl.WL_FP64, "fp64")):
+        log(f"[bench] c3 {name}")
+        wl.wl_set_timing(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wl.wl_average_ex_device(ctx, ens, fld, d_rho, d_T, 1, prec, outs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        k_ms, _ = wl.wl_kernel_ms_total(ctx)
+        wl.wl_set_timing(ctx, False)
+        res[name] = ({k: v.cpu().numpy() for k, v in outs.items()},
+                     {"call_s": dt, "kernel_ms": k_ms, "segment_evals_per_s": segs / dt})
+        log(f"[bench] c3 {name}: {dt:.2f} s, main kernel {k_ms:.1f} ms")
+    wl.wl_ensemble_free(ens)
+    out = {"workload": "sech2 B0=20 lam=4 spinor, 131072 x 8192 loops, 32 x 48 grid",
+           "segment_evals": segs, "fp32c": res["fp32c"][1], "fp64": res["fp64"][1],
+           "fp32c_over_fp64": res["fp64"][1]["call_s"] / res["fp32c"][1]["call_s"]}
+    r64 = dict(res["fp64"][0], err=None)
+    out["fp32c_vs_fp64"] = precision_report(res["fp32c"][0], r64)
+    out["finite"] = bool(np.isfinite(res["fp32c"][0]["mean"]).all())
+    return out
+
+
+def committed_issue_frac(workload, kernel_ms):
+    """Share of the SIMDs' issue cycles the main kernel's VALU work fills:
+    its wave-instruction counts per launch (profiles/k_average_<workload>.md,
+    line "valu: fp32=A trans=B fp64=C source=H", from rocprofv3 counters)
+    each divided by the chip's measured issue rate for that class
+    (profiles/valu_issue_rates.md, line "rates: fp32=R1 trans=R2 fp64=R3",
+    wave-instructions per second over the whole chip), over the kernel's
+    duration.  None when either file lacks the line or the counters are
+    stale (kernel source hash H differs)."""
+    import re
+    p1 = os.path.join(PROFILES, f"k_average_{workload}.md")
+    p2 = os.path.join(PROFILES, "valu_issue_rates.md")
+    if not (os.path.exists(p1) and os.path.exists(p2)):
+        return None
+    m1 = re.search(r"valu: fp32=([\d.e+]+) trans=([\d.e+]+) fp64=([\d.e+]+) "
+                   r"source=([0-9a-f]+)", open(p1).read())
+    m2 = re.search(r"rates: fp32=([\d.e+]+) trans=([\d.e+]+) fp64=([\d.e+]+)",
+                   open(p2).read())
+    if not (m1 and m2) or m1.group(4) != kernel_source_hash():
+        return None
+    n = [float(v) for v in m1.groups()[:3]]
+    r = [float(v) for v in m2.groups()]
+    return sum(a / b for a, b in zip(n, r)) / (kernel_ms * 1e-3)
 
 
 def batch_run(args):
@@ -162,17 +287,29 @@ def main():
                     help="Poisson arrival rate of the serving run, requests/s")
     ap.add_argument("--serve-loops", type=int, default=16384,
                     help="loops of the serving ensemble (4096 points each)")
+    ap.add_argument("--serve-rate-low", type=float, default=4.0,
+                    help="arrival rate of the serving point below capacity, requests/s")
+    ap.add_argument("--serve-requests-low", type=int, default=16,
+                    help="requests of the serving point below capacity")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip the precision-stress evaluation (131072 x 8192 loops, "
+                         "32 x 48 grid, sech^2 B0 = 20, lambda = 4, spinor)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving run (prints its JSON) and exit")
     ap.add_argument("--batch-requests", type=int, default=0,
                     help="only a batched evaluation of this many uneven requests "
                          "(request seed 1) on the workload's ensemble, then exit")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only measure the VALU issue rates (probe library) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes "
                          "(5 times; reference for HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.valu_rates:
+        valu_rates()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -183,7 +320,8 @@ def main():
 
         import paper_1407_7486_amd as wl
         ctx = wl.wl_create(0, torch.cuda.current_stream().cuda_stream)
-        print(json.dumps({"serve": serve_run(wl, ctx, args)}), flush=True)
+        print(json.dumps({"serve": serve_run(wl, ctx, args.serve_rate, args.serve_requests,
+                                             args.serve_loops)}), flush=True)
         wl.wl_destroy(ctx)
         return
     if args.batch_requests:
@@ -220,42 +358,66 @@ def main():
     d_sums = torch.empty((G, rho.size, T.size), dtype=torch.float64, device=dev)
     d_mean = torch.empty((rho.size, T.size), dtype=torch.float64, device=dev)
     d_err = torch.empty_like(d_mean)
+    d_scale = torch.empty_like(d_mean)
+    d_fperr = torch.empty_like(d_mean)
+    d_esc = torch.empty((rho.size, T.size), dtype=torch.uint8, device=dev)
+    outs = {"mean": d_mean, "err": d_err, "group_sums": d_sums, "scale": d_scale,
+            "fp_err": d_fperr, "escalated": d_esc}
     fld = wl.field(kind, cfg["eB0"], cfg["lam"])
 
-    def run(prec, warmup, steps):
+    def run(ens_, rho_d, T_d, prec, warmup, steps, outs_):
         for _ in range(warmup):
-            wl.wl_average_async(ctx, ens, fld, d_rho, d_T, spin, prec, d_mean, d_err, d_sums)
+            wl.wl_average_ex_device(ctx, ens_, fld_, rho_d, T_d, spin, prec, outs_)
         torch.cuda.synchronize()
         wl.wl_set_timing(ctx, True)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for i in range(steps):
-            wl.wl_average_async(ctx, ens, fld, d_rho, d_T, spin, prec, d_mean, d_err, d_sums)
+            wl.wl_average_ex_device(ctx, ens_, fld_, rho_d, T_d, spin, prec, outs_)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t_start
         k_ms, n = wl.wl_kernel_ms_total(ctx)
         wl.wl_set_timing(ctx, False)
-        if not bool(torch.isfinite(d_mean).all()):
+        if not bool(torch.isfinite(outs_["mean"]).all()):
             raise RuntimeError("non-finite result")
         return dt, k_ms / n
 
+    def host(outs_):
+        return {k: v.cpu().numpy() for k, v in outs_.items()}
+
+    def precision_report(r32, r64):
+        """FP32C against FP64 on the same ensemble, in units of the mean
+        tolerance 1e-6 M_S (M_S the scale each mean carries), with the
+        library's own rounding estimates and the share it recomputed."""
+        bar = 1e-6 * r64["scale"]
+        d = np.abs(r32["mean"] - r64["mean"])
+        kappa = r64["scale"] / np.maximum(np.abs(r64["mean"]), 1e-300)
+        return {"max_mean_diff_over_bar": float(np.max(d / bar)),
+                "points_beyond_bar": int(np.sum(d > bar)),
+                "max_stated_fp_err_over_bar": float(np.max(r32["fp_err"] / bar)),
+                "diff_within_stated_fp_err": bool(np.all(d <= r32["fp_err"] + r64["fp_err"])),
+                "escalated_points": int(r32["escalated"].sum()),
+                "escalated_fraction": float(r32["escalated"].mean()),
+                "kappa_max": float(np.max(kappa)), "kappa_median": float(np.median(kappa))}
+
+    fld_ = fld
     log(f"[bench] fp32c: warmup {args.warmup}, steps {args.steps}")
-    dt, k_ms = run(wl.WL_FP32C, args.warmup, args.steps)
+    dt, k_ms = run(ens, d_rho, d_T, wl.WL_FP32C, args.warmup, args.steps, outs)
     value = seg_per_step * args.steps / dt
     log(f"[bench] fp32c {value:.4e} seg/s, kernel {k_ms:.1f} ms")
-    mean32 = d_mean.cpu().numpy()
+    r32 = host(outs)
     fp64 = None
     if args.fp64_steps > 0:
         log(f"[bench] fp64: steps {args.fp64_steps}")
-        dt64, k64 = run(wl.WL_FP64, 0, args.fp64_steps)
+        dt64, k64 = run(ens, d_rho, d_T, wl.WL_FP64, 0, args.fp64_steps, outs)
         v64 = seg_per_step * args.fp64_steps / dt64
-        mean64 = d_mean.cpu().numpy()
-        scale = np.maximum(np.abs(mean64), 1.0)
+        r64 = host(outs)
         fp64 = {"value": v64, "ms_per_step": 1e3 * dt64 / args.fp64_steps,
                 "kernel_ms": k64, "steps": args.fp64_steps,
                 "fp32c_over_fp64": value / v64,
-                "max_rel_mean_diff_fp32c_vs_fp64": float(np.max(np.abs(mean32 - mean64) / scale))}
-        log(f"[bench] fp64 {v64:.4e} seg/s, kernel {k64:.1f} ms")
+                "fp32c_vs_fp64": precision_report(r32, r64)}
+        log(f"[bench] fp64 {v64:.4e} seg/s, kernel {k64:.1f} ms; "
+            f"{fp64['fp32c_vs_fp64']}")
 
     disc = None
     if args.disc_steps > 0 and cfg["n_ppl"] % 4 == 0:
@@ -339,13 +501,21 @@ def main():
         log(f"[bench] device generation {kg:.1f} ms ({npts / (kg * 1e-3):.3e} points/s), "
             f"CPU generator {t_cpu_gen:.1f} s, identical {same:.6f}")
 
-    slots = SLOTS_FP32C[(kname, spin)]
+    slots = SLOTS[(kname, spin)]
     achieved = seg_per_step * slots / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
-                "unit": "Top/s (FP32 VALU lane-ops)", "frac": achieved / PEAK_OPS,
-                "traffic": TRAFFIC.get(args.workload),
+    traffic, traffic_src = committed_traffic(args.workload)
+    issue = committed_issue_frac(args.workload, k_ms)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s (FP32 VALU slot-equivalents: 1 per operation, "
+                        "4 per transcendental)",
+                "frac": achieved / PEAK_FP32, "traffic": traffic,
+                "traffic_source_hash": traffic_src, "kernel_source_hash": kernel_source_hash(),
                 "kernel": f"k_average<{kname},spin={spin},fp32c>", "kernel_ms": k_ms,
-                "ops_per_segment": slots}
+                "ops_per_segment": slots, "issue_frac": issue}
+
+    c3 = None
+    if args.c3:
+        c3 = c3_run(wl, ctx, torch, dev, precision_report)
 
     cpu = None
     if args.cpu_loops > 0:
@@ -385,10 +555,12 @@ def main():
             f"({oracle.max_threads()} threads), {dtc1_1:.2f} s on 1 thread")
 
     wl.wl_ensemble_free(ens)
-    serve = None
+    serve = serve_low = None
     if args.serve_requests > 0:
         del x, y
-        serve = serve_run(wl, ctx, args)
+        serve_low = serve_run(wl, ctx, args.serve_rate_low, args.serve_requests_low,
+                              args.serve_loops)
+        serve = serve_run(wl, ctx, args.serve_rate, args.serve_requests, args.serve_loops)
     wl.wl_destroy(ctx)
     out = {
         "metric": METRIC, "value": value, "unit": "segment-evals/s", "n_gpus": 1,
@@ -399,8 +571,8 @@ def main():
                    "n_ppl": cfg["n_ppl"], "n_rho": int(rho.size), "n_T": int(T.size),
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
-        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "serve": serve,
-        "disc": disc, "generate": gen, "correlation": corr,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "c3": c3, "serve": serve,
+        "serve_sub_capacity": serve_low, "disc": disc, "generate": gen, "correlation": corr,
     }
     print(json.dumps(out), flush=True)
 

@@ -71,10 +71,14 @@ typedef struct wl_field {
 } wl_field;
 
 /* ---- precision modes ---------------------------------------------------
-  * WL_FP32C  FP32 segment arithmetic; phase and spin sums compensated (FP32
+ * WL_FP32C  FP32 segment arithmetic; phase and spin sums compensated (FP32
  *           sums over blocks of 32 segments, the block sums accumulated in
- *           FP64); FP64 per-loop epilogue and FP64 group sums.
- * WL_FP32   the same with plain FP32 sums (precision-study mode).
+ *           FP64); FP64 per-loop epilogue and FP64 group sums.  Guarded by
+ *           a rounding estimate: per-loop values whose FP32 phase may miss
+ *           the phase tolerance 1e-5 max(1, |Phi|), and ensemble means whose
+ *           estimated rounding error exceeds half the mean tolerance
+ *           1e-6 M_S (see wl_result), are recomputed in FP64.
+ * WL_FP32   plain FP32 sums, no guard (precision-study mode).
  * WL_FP64   FP64 throughout.                                               */
 #define WL_FP32C 0
 #define WL_FP32 1
@@ -173,6 +177,47 @@ int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                int32_t spin, int32_t precision, double* mean, double* err,
                double* group_sums);
 
+/* Results of an evaluation (each pointer may be NULL; see wl_average_ex).
+ * With w_l = cos(Phi_l) cosh(S_l) per loop and N_l loops:
+ *   mean       [n_rho][n_T]    (1/N_l) sum_l w_l
+ *   err        [n_rho][n_T]    standard error of the group means
+ *   group_sums [G][n_rho][n_T] sum of w over each group's loops
+ *   scale      [n_rho][n_T]    M_S = (1/N_l) sum_l |w_l| max(1, S_l): the
+ *                              size of the terms the mean cancels (for
+ *                              scalars the mean |w|; Sec. 4.3, the fermion
+ *                              problem).  M_S / |mean| is the conditioning
+ *                              of the mean, and the mean's rounding
+ *                              tolerance is 1e-6 M_S.
+ *   fp_err     [n_rho][n_T]    estimated rounding error of the mean: from
+ *                              each loop's phase-sum rounding, 32 u
+ *                              sqrt(sum_i t_i^2) over its segment terms t_i,
+ *                              carried to the mean through sin(Phi) cosh(S)
+ *                              and added in quadrature, plus 8 u M_S for the
+ *                              roundings shared by all loops (u = 2^-24 for
+ *                              the FP32 modes, 2^-53 for FP64 and for
+ *                              recomputed points)
+ *   escalated  [n_rho][n_T]    1 where WL_FP32C recomputed the point in FP64
+ *                              (the random part of fp_err above 0.5e-6 M_S),
+ *                              else 0 */
+typedef struct wl_result {
+  double* mean;
+  double* err;
+  double* group_sums;
+  double* scale;
+  double* fp_err;
+  uint8_t* escalated;
+} wl_result;
+
+/* wl_average with every output of wl_result.  flags WL_HOST_PTR: rho, T
+ * and the outputs are host memory and the call is synchronous (as
+ * wl_average); WL_DEVICE_PTR: they are device memory on the ctx device,
+ * group_sums is required and the call only enqueues work on the ctx stream
+ * (as wl_average_async, whose grid requirements apply).
+ * Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
+int wl_average_ex(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                  const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                  int32_t spin, int32_t precision, int32_t flags, const wl_result* out);
+
 /* As wl_average, but every array is DEVICE memory on the ctx device and
  * the call only enqueues work on the ctx stream (no host synchronisation).
  * d_rho, d_T must stay valid and unchanged until the work completes, and
@@ -186,23 +231,24 @@ int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
                      double* d_mean, double* d_err, double* d_group_sums);
 
 /* Largest device scratch the allocation-free evaluation can use. */
-#define WL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define WL_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 
 /* As wl_average_async, for callers that cannot allocate device memory:
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments, kernels and results (bit for bit) as
  * wl_average_async; the call allocates nothing (no hipMalloc / hipFree, no
  * event creation) and records no kernel timing.  Its only scratch, the
- * sub-range partial sums G * n_sub * n_rho * n_T * 8 bytes (n_sub the
- * library's split of each group's loops, at most 64, 1 when a group is
- * small or the grid large), lives in a static device array of
- * WL_NOALLOC_SCRATCH_BYTES per device, reserved when the library is loaded
- * and held until the process ends.  Every call on a device shares that
+ * item sums of the evaluation (w when a group's loops are split, and the
+ * scale and rounding accumulators: 8 (2 or 3) G n_sub n_rho n_T bytes, n_sub
+ * the library's split of each group's loops, at most 64, 1 when a group is
+ * small or the grid large) and one flag byte per grid point, lives in a
+ * static device array of WL_NOALLOC_SCRATCH_BYTES per device, reserved when
+ * the library is loaded and held until the process ends.  Every call on a device shares that
  * array: calls that overlap on one device (two contexts or streams)
  * race and must be serialised by the caller.  Nothing in the array needs
  * to start at zero.
- * Errors: WL_EINVAL as wl_average_async, and also when the partial sums
- * would exceed WL_NOALLOC_SCRATCH_BYTES (message gives both sizes) or when
+ * Errors: WL_EINVAL as wl_average_async, and also when the scratch would
+ * exceed WL_NOALLOC_SCRATCH_BYTES (message gives both sizes) or when
  * precision is WL_FP64 and the ensemble's FP64 segment array does not exist
  * yet (an FP64 wl_average or wl_average_async derives it); WL_EHIP when the
  * scratch array's device address could not be obtained at wl_create. */
@@ -224,6 +270,9 @@ typedef struct wl_request {
   double* mean;       /* [n_rho][n_T] */
   double* err;        /* [n_rho][n_T] */
   double* group_sums; /* [G][n_rho][n_T] */
+  double* scale;      /* [n_rho][n_T], as wl_result */
+  double* fp_err;     /* [n_rho][n_T], as wl_result */
+  uint8_t* escalated; /* [n_rho][n_T], as wl_result */
 } wl_request;
 
 /* Batched evaluation of n_reqs uneven requests (different fields, grids,
@@ -297,6 +346,9 @@ int wl_server_destroy(wl_server* srv);
  *   phase     Phi in radians
  *   spin_exp  S = e int_0^T B dtau (0 is written when spin == 0)
  *   w         cos(Phi) * (spin ? cosh(S) : 1)
+ * WL_FP32C: a (loop, point) whose estimated FP32 phase rounding, 32 u
+ * sqrt(sum_i t_i^2) over its segment terms t_i, exceeds the phase tolerance
+ * 1e-5 max(1, |Phi|) is recomputed in FP64 (all three values).
  * n_loops * n_rho * n_T must not exceed 2^27.
  * Synchronous.  Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
 int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,

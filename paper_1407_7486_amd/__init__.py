@@ -25,7 +25,7 @@ WL_FP32C, WL_FP32, WL_FP64 = 0, 1, 2
 WL_HOST_PTR, WL_DEVICE_PTR = 0, 1
 WL_DISC_PAPER, WL_DISC_FULL = 0, 1
 WL_SUB_CIRCLE, WL_SUB_SQUARE, WL_SUB_TRIANGLE = 0, 1, 2
-WL_NOALLOC_SCRATCH_BYTES = 64 << 20
+WL_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 # every entry point declared in include/wl.h
 EXPORTS = (
@@ -37,7 +37,7 @@ EXPORTS = (
     "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
     "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
     "wl_ensemble_generate", "wl_ensemble_download", "wl_ensemble_set_groups",
-    "wl_correlation", "wl_regroup", "wl_average_async_noalloc",
+    "wl_correlation", "wl_regroup", "wl_average_async_noalloc", "wl_average_ex",
 )
 
 
@@ -57,7 +57,13 @@ class wl_request(ctypes.Structure):
                 ("n_rho", ctypes.c_int32), ("n_T", ctypes.c_int32),
                 ("spin", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("err", ctypes.c_void_p),
-                ("group_sums", ctypes.c_void_p)]
+                ("group_sums", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("fp_err", ctypes.c_void_p), ("escalated", ctypes.c_void_p)]
+
+
+class wl_result(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "mean", "err", "group_sums", "scale", "fp_err", "escalated")]
 
 
 class wl_action_spec(ctypes.Structure):
@@ -111,6 +117,8 @@ _sigs = {
                     _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "wl_average_async": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp,
                           _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "wl_average_ex": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32, _i32, _i32,
+                       _i32, ctypes.POINTER(wl_result)], ctypes.c_int),
     "wl_average_async_noalloc": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp,
                                   _i32, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
     "wl_per_loop": ([_vp, _vp, ctypes.POINTER(wl_field), _vp, _i32, _vp, _i32,
@@ -293,6 +301,41 @@ def wl_average(ctx, ens, fld, rho, T, spin, precision=WL_FP32C):
     return mean, err, sums
 
 
+RESULT_KEYS = ("mean", "err", "group_sums", "scale", "fp_err", "escalated")
+
+
+def _result_arrays(G, n_rho, n_T):
+    return {"mean": np.zeros((n_rho, n_T)), "err": np.zeros((n_rho, n_T)),
+            "group_sums": np.zeros((G, n_rho, n_T)), "scale": np.zeros((n_rho, n_T)),
+            "fp_err": np.zeros((n_rho, n_T)),
+            "escalated": np.zeros((n_rho, n_T), dtype=np.uint8)}
+
+
+def wl_average_ex(ctx, ens, fld, rho, T, spin, precision=WL_FP32C):
+    """Synchronous average with every output of wl_result; returns a dict
+    of numpy arrays: mean, err, scale, fp_err, escalated (n_rho, n_T) and
+    group_sums (G, n_rho, n_T)."""
+    rho = _host_f64(rho)
+    T = _host_f64(T)
+    _, _, G = wl_ensemble_info(ens)
+    out = _result_arrays(G, rho.size, T.size)
+    res = wl_result(*[_ptr(out[k]) for k in RESULT_KEYS])
+    _check(_lib.wl_average_ex(ctx, ens, ctypes.byref(fld), _ptr(rho), rho.size, _ptr(T),
+                              T.size, int(spin), int(precision), WL_HOST_PTR,
+                              ctypes.byref(res)), ctx)
+    return out
+
+
+def wl_average_ex_device(ctx, ens, fld, d_rho, d_T, spin, precision, outs):
+    """Enqueue an average on the context stream; d_rho, d_T and the values
+    of `outs` (keys of RESULT_KEYS, group_sums required) are torch device
+    tensors."""
+    res = wl_result(*[_ptr(outs.get(k)) for k in RESULT_KEYS])
+    _check(_lib.wl_average_ex(ctx, ens, ctypes.byref(fld), _ptr(d_rho), d_rho.numel(),
+                              _ptr(d_T), d_T.numel(), int(spin), int(precision),
+                              WL_DEVICE_PTR, ctypes.byref(res)), ctx)
+
+
 def wl_discretisation(ctx, ens, fld, rho, T, spin, precision=WL_FP32C, mode=WL_DISC_PAPER):
     """Discretisation estimate (levels N, N/2, N/4, extrapolated); returns
     (mean, err, delta, group_sums) of shapes (4, n_rho, n_T), (4, n_rho,
@@ -375,26 +418,31 @@ def wl_average_async_noalloc(ctx, ens, fld, d_rho, d_T, spin, precision, d_mean,
                                          _ptr(d_err), _ptr(d_group_sums)), ctx)
 
 
-def wl_average_batch(ctx, ens, requests):
+def _request(q, G, keep):
+    rho = _host_f64(q["rho"])
+    T = _host_f64(q["T"])
+    out = _result_arrays(G, rho.size, T.size)
+    keep += [rho, T]
+    req = wl_request(field(q["kind"], q["eB0"], q.get("lam", 1.0)), _ptr(rho), _ptr(T),
+                     rho.size, T.size, int(q["spin"]), int(q.get("precision", WL_FP32C)),
+                     *[_ptr(out[k]) for k in RESULT_KEYS])
+    return req, out
+
+
+def wl_average_batch(ctx, ens, requests, full=False):
     """Batched evaluation.  requests: list of dicts with keys kind, eB0, lam,
-    rho, T, spin, precision.  Returns a list of (mean, err, group_sums)."""
+    rho, T, spin, precision.  Returns a list of (mean, err, group_sums), or
+    with full=True of dicts with every output of wl_result."""
     _, _, G = wl_ensemble_info(ens)
     arr = (wl_request * max(1, len(requests)))()
     keep, outs = [], []
     for i, q in enumerate(requests):
-        rho = _host_f64(q["rho"])
-        T = _host_f64(q["T"])
-        mean = np.zeros((rho.size, T.size))
-        err = np.zeros((rho.size, T.size))
-        sums = np.zeros((G, rho.size, T.size))
-        keep += [rho, T]
-        outs.append((mean, err, sums))
-        arr[i] = wl_request(field(q["kind"], q["eB0"], q.get("lam", 1.0)), _ptr(rho), _ptr(T),
-                            rho.size, T.size, int(q["spin"]),
-                            int(q.get("precision", WL_FP32C)),
-                            _ptr(mean), _ptr(err), _ptr(sums))
+        arr[i], out = _request(q, G, keep)
+        outs.append(out)
     _check(_lib.wl_average_batch(ctx, ens, arr, len(requests)), ctx)
-    return outs
+    if full:
+        return outs
+    return [(o["mean"], o["err"], o["group_sums"]) for o in outs]
 
 
 class Server:
@@ -416,14 +464,9 @@ class Server:
 
     def submit(self, q):
         """q: dict with kind, eB0, lam, rho, T, spin, precision.  Returns a
-        ticket; outputs (mean, err, group_sums) via result()."""
-        rho = _host_f64(q["rho"])
-        T = _host_f64(q["T"])
-        out = (np.zeros((rho.size, T.size)), np.zeros((rho.size, T.size)),
-               np.zeros((self.G, rho.size, T.size)))
-        req = wl_request(field(q["kind"], q["eB0"], q.get("lam", 1.0)), _ptr(rho), _ptr(T),
-                         rho.size, T.size, int(q["spin"]), int(q.get("precision", WL_FP32C)),
-                         _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        ticket; outputs via result()."""
+        keep = []
+        req, out = _request(q, self.G, keep)
         t = _i64()
         self._check(_lib.wl_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
         self._live[t.value] = out
@@ -440,12 +483,16 @@ class Server:
                                         ctypes.byref(lat)))
         return st.value, lat.value
 
-    def result(self, ticket, release=True):
+    def result(self, ticket, release=True, full=False):
+        """(mean, err, group_sums) of a finished ticket, or with full=True the
+        dict of every output of wl_result."""
         out = self._live[ticket]
         if release:
             self._check(_lib.wl_server_release(self.h, ticket))
             del self._live[ticket]
-        return out
+        if full:
+            return out
+        return out["mean"], out["err"], out["group_sums"]
 
     def info(self):
         a, b, c = _i64(), _i64(), _i64()

@@ -1,4 +1,5 @@
-"""Compile the gfx950 HIP library libwl.so in-tree with hipcc."""
+"""Compile the gfx950 HIP library libwl.so in-tree with hipcc, and the VALU
+issue-rate probe libwl_probe.so that bench.py --valu-rates runs."""
 from __future__ import annotations
 
 import os
@@ -7,6 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwl.so")
+PROBE_LIB = os.path.join(HERE, "libwl_probe.so")
+PROBE_SOURCES = ["valu_rates.hip"]
 SOURCES = ["wl_api.hip", "wl_kernels.hip", "wl_server.hip", "wl_action.hip",
            "wl_generate.hip", "wl_corr.hip"]
 
@@ -22,9 +25,15 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    _compile(SOURCES, LIB, verbose)
+    _compile(PROBE_SOURCES, PROBE_LIB, verbose)
+    return LIB
+
+
+def _compile(sources, lib, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *[os.path.join(CSRC, s) for s in SOURCES],
+    tmp = lib + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *[os.path.join(CSRC, s) for s in sources],
            "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -37,8 +46,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msg}")
     if verbose and msg.strip():
         print(msg)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

@@ -158,8 +158,14 @@ ReqPlan plan_request(const wl_ctx* ctx, const wl_ens* ens, const wl_request& q) 
   p.s = make_sched(ctx, ens, p.n_pts);
   const int64_t G = ens->n_groups;
   p.in_bytes = sizeof(ReqDesc) + 8 * (size_t)(q.n_rho + q.n_T);
-  p.res_bytes = 8 * (size_t)(G * p.n_pts + 2 * p.n_pts +
-                             (p.s.n_sub > 1 ? G * p.s.n_sub * p.n_pts : 0));
+  // group sums, mean, err, scale, fp_err, escalation flags (one byte per
+  // point, padded to 8 with the other requests'), the item scale and
+  // rounding accumulators, and the item partial sums of w when split
+  const size_t part = (size_t)G * p.s.n_sub * p.n_pts;
+  // (+ the compacted list of flagged points and its count)
+  p.res_bytes = 8 * ((size_t)G * p.n_pts + 4 * (size_t)p.n_pts + 2 * part +
+                     (p.s.n_sub > 1 ? part : 0)) +
+                (size_t)p.n_pts + 8 + 4 * (size_t)p.n_pts + 8;
   return p;
 }
 
@@ -173,12 +179,16 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
     lay->items += plans[i].s.n_items;
     lay->sums_n += G * plans[i].n_pts;
     lay->pts_n += plans[i].n_pts;
+    lay->acc_n += G * plans[i].s.n_sub * plans[i].n_pts;
     if (plans[i].s.n_sub > 1) lay->part_n += G * plans[i].s.n_sub * plans[i].n_pts;
     grid_n += reqs[i]->n_rho + reqs[i]->n_T;
   }
   const size_t grids_off = kBatchDescOffset + (((size_t)n * sizeof(ReqDesc) + 255) & ~(size_t)255);
   lay->in_bytes = grids_off + 8 * (size_t)grid_n;
-  lay->res_bytes = 8 * (size_t)(lay->sums_n + 2 * lay->pts_n + lay->part_n);
+  lay->head_bytes = 8 * (size_t)(lay->sums_n + 4 * lay->pts_n) +
+                    (((size_t)lay->pts_n + 7) & ~(size_t)7);
+  lay->res_bytes = lay->head_bytes + 8 * (size_t)(2 * lay->acc_n + lay->part_n) +
+                   4 * (size_t)(lay->pts_n + n) + 8;
   if (lay->in_bytes > cap_in || lay->res_bytes > cap_res) return false;
   char* hb = (char*)h_in;
   BatchHeader* hdr = (BatchHeader*)hb;
@@ -189,9 +199,17 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
   ReqDesc* desc = (ReqDesc*)(hb + kBatchDescOffset);
   double* h_grid = (double*)(hb + grids_off);
   const double* d_grid = (const double*)((const char*)d_in + grids_off);
+  // [sums | mean | err | scale | fp_err | flags (bytes) | acc a | acc v | partials]
   double* d_sums = (double*)d_res;
-  double* d_part = d_sums + lay->sums_n + 2 * lay->pts_n;
-  int64_t items = 0, sums = 0, pts = 0, part = 0, go = 0;
+  double* d_scale = d_sums + lay->sums_n + 2 * lay->pts_n;
+  double* d_fperr = d_scale + lay->pts_n;
+  uint8_t* d_flags = (uint8_t*)(d_fperr + lay->pts_n);
+  double* d_acc_a = (double*)((char*)d_res + lay->head_bytes);
+  double* d_acc_v = d_acc_a + lay->acc_n;
+  double* d_part = d_acc_v + lay->acc_n;
+  int32_t* d_list = (int32_t*)(d_part + lay->part_n);  // [pts_n] lists, then [n] counts
+  int32_t* d_count = d_list + lay->pts_n;
+  int64_t items = 0, sums = 0, pts = 0, part = 0, acc = 0, go = 0;
   for (int32_t i = 0; i < n; ++i) {
     const wl_request& q = *reqs[i];
     const ReqPlan& pl = plans[i];
@@ -203,6 +221,13 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
     memcpy(h_grid + go + q.n_rho, q.T, q.n_T * sizeof(double));
     go += q.n_rho + q.n_T;
     e.out = pl.s.n_sub > 1 ? d_part + part : d_sums + sums;
+    e.out_a = d_acc_a + acc;
+    e.out_v = d_acc_v + acc;
+    e.scale = d_scale + pts;
+    e.fp_err = d_fperr + pts;
+    e.flags = d_flags + pts;
+    e.list = d_list + pts;
+    e.count = d_count + i;
     e.item_begin = items;
     e.loops_per_sub = pl.s.loops_per_sub;
     e.sums_begin = sums;
@@ -218,6 +243,7 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
     items += pl.s.n_items;
     sums += G * pl.n_pts;
     pts += pl.n_pts;
+    acc += G * pl.s.n_sub * pl.n_pts;
     if (pl.s.n_sub > 1) part += G * pl.s.n_sub * pl.n_pts;
   }
   return true;
@@ -226,11 +252,16 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
 void scatter_results(const wl_request& q, const BatchLayout& lay, int32_t i,
                      const double* h_res, int64_t G) {
   const int64_t n_pts = (int64_t)q.n_rho * q.n_T;
+  const double* per_pt = h_res + lay.sums_n + lay.pts_begin[i];
   if (q.group_sums)
     memcpy(q.group_sums, h_res + lay.sums_begin[i], G * n_pts * sizeof(double));
-  if (q.mean) memcpy(q.mean, h_res + lay.sums_n + lay.pts_begin[i], n_pts * sizeof(double));
-  if (q.err)
-    memcpy(q.err, h_res + lay.sums_n + lay.pts_n + lay.pts_begin[i], n_pts * sizeof(double));
+  if (q.mean) memcpy(q.mean, per_pt, n_pts * sizeof(double));
+  if (q.err) memcpy(q.err, per_pt + lay.pts_n, n_pts * sizeof(double));
+  if (q.scale) memcpy(q.scale, per_pt + 2 * lay.pts_n, n_pts * sizeof(double));
+  if (q.fp_err) memcpy(q.fp_err, per_pt + 3 * lay.pts_n, n_pts * sizeof(double));
+  if (q.escalated)
+    memcpy(q.escalated,
+           (const uint8_t*)(h_res + lay.sums_n + 4 * lay.pts_n) + lay.pts_begin[i], n_pts);
 }
 
 // Event pair for the next timed launch (created on first use).
@@ -351,7 +382,7 @@ int wl_create(wl_ctx** out, int device, void* hip_stream) {
   c->num_cu = prop.multiProcessorCount;
   DeviceGuard g(device);
   if (g.status != hipSuccess || hipMalloc((void**)&c->d_flag, sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&c->d_counter, sizeof(unsigned int)) != hipSuccess) {
+      hipMalloc((void**)&c->d_counter, 2 * sizeof(unsigned int)) != hipSuccess) {
     wl_destroy(c);
     return WL_ENOMEM;
   }
@@ -413,12 +444,14 @@ int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
     if (e->d_x) (void)hipFree(e->d_x);
     if (e->d_y) (void)hipFree(e->d_y);
     if (e->d_seg) (void)hipFree(e->d_seg);
+    if (e->d_norm) (void)hipFree(e->d_norm);
     delete e;
     return code;
   };
   if (hipMalloc((void**)&e->d_x, npts * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&e->d_y, npts * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess) {
+      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess ||
+      hipMalloc((void**)&e->d_norm, n_loops * sizeof(float2)) != hipSuccess) {
     (void)hipGetLastError();
     return cleanup(fail(ctx, WL_ENOMEM, "device allocation of %lld points failed",
                         (long long)npts));
@@ -430,7 +463,8 @@ int wl_ensemble_upload(wl_ctx* ctx, const float* y_x, const float* y_y,
     err = hipMemcpyAsync(e->d_y, y_y, npts * sizeof(float), kind, ctx->stream);
   if (err == hipSuccess) err = hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream);
   if (err == hipSuccess)
-    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, ctx->d_flag, ctx->stream);
+    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, e->d_norm, ctx->d_flag,
+                           ctx->stream);
   int bad = 0;
   if (err == hipSuccess)
     err = hipMemcpyAsync(&bad, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
@@ -467,12 +501,14 @@ int wl_ensemble_generate(wl_ctx* ctx, uint64_t seed, int64_t first_loop, int64_t
     if (e->d_x) (void)hipFree(e->d_x);
     if (e->d_y) (void)hipFree(e->d_y);
     if (e->d_seg) (void)hipFree(e->d_seg);
+    if (e->d_norm) (void)hipFree(e->d_norm);
     delete e;
     return code;
   };
   if (hipMalloc((void**)&e->d_x, npts * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&e->d_y, npts * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess) {
+      hipMalloc((void**)&e->d_seg, npts * sizeof(float4)) != hipSuccess ||
+      hipMalloc((void**)&e->d_norm, n_loops * sizeof(float2)) != hipSuccess) {
     (void)hipGetLastError();
     return cleanup(fail(ctx, WL_ENOMEM, "device allocation of %lld points failed",
                         (long long)npts));
@@ -491,7 +527,8 @@ int wl_ensemble_generate(wl_ctx* ctx, uint64_t seed, int64_t first_loop, int64_t
   }
   if (err == hipSuccess) err = hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream);
   if (err == hipSuccess)
-    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, ctx->d_flag, ctx->stream);
+    err = wl::launch_prep(e->d_x, e->d_y, n_loops, n_ppl, e->d_seg, e->d_norm, ctx->d_flag,
+                           ctx->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
   if (err != hipSuccess) return cleanup(hip_fail(ctx, err, "ensemble generation"));
   *out = e;
@@ -530,6 +567,7 @@ int wl_ensemble_free(wl_ens* ens) {
   (void)hipFree(ens->d_x);
   (void)hipFree(ens->d_y);
   (void)hipFree(ens->d_seg);
+  (void)hipFree(ens->d_norm);
   if (ens->d_sub) (void)hipFree(ens->d_sub);
   if (ens->d_seg64) (void)hipFree(ens->d_seg64);
   if (ens->d_sub64) (void)hipFree(ens->d_sub64);
@@ -597,14 +635,35 @@ static int need_seg64(wl_ctx* ctx, const wl_ens* ens) {
   return WL_OK;
 }
 
-// Enqueue one evaluation; grid and outputs are device memory.  With
-// `noalloc` the call allocates nothing: the partial sums go to the static
-// scratch array (ctx->d_noalloc), the FP64 segment array must exist
+// Device outputs of one evaluation (each may be NULL but sums).
+struct DevOut {
+  double* sums;   // [G][n_pts]
+  double* mean;   // [n_pts]
+  double* err;
+  double* scale;
+  double* fp_err;
+  uint8_t* escalated;
+};
+
+// Scratch of one evaluation: the item partial sums of w (when a group's
+// loops are split), of the scale and rounding accumulators, the FP64
+// recomputation flags and the compacted list of flagged points with its
+// count.
+static size_t flag_bytes(int32_t n_pts) { return ((size_t)n_pts + 7) & ~(size_t)7; }
+static size_t eval_scratch_bytes(const wl::Sched& s, int64_t n_groups, int32_t n_pts) {
+  const size_t part = (size_t)n_groups * s.n_sub * n_pts;
+  return 8 * part * (s.n_sub > 1 ? 3 : 2) + flag_bytes(n_pts) + 4 * ((size_t)n_pts + 1);
+}
+
+// Enqueue one evaluation; grid and outputs are device memory: the main
+// kernel, the per-point scale and rounding estimate (and for WL_FP32C the
+// FP64 recomputation of the flagged points), the sub-range reduction and
+// the statistics.  With `noalloc` the call allocates nothing: the scratch
+// is the static array (ctx->d_noalloc), the FP64 segment array must exist
 // already, and no timing events are recorded.
 static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa,
                           const double* d_rho, int32_t n_rho, const double* d_T,
-                          int32_t n_T, int32_t spin, int32_t precision,
-                          double* d_mean, double* d_err, double* d_sums,
+                          int32_t n_T, int32_t spin, int32_t precision, const DevOut& o,
                           bool noalloc = false) {
   const int32_t n_pts = n_rho * n_T;
   if (precision == WL_FP64) {
@@ -619,21 +678,25 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
     }
   }
   const wl::Sched s = make_sched(ctx, ens, n_pts);
-  double* main_out = d_sums;
-  if (s.n_sub > 1) {
-    const size_t need = (size_t)ens->n_groups * s.n_sub * n_pts * sizeof(double);
-    if (noalloc) {
-      if (need > WL_NOALLOC_SCRATCH_BYTES)
-        return fail(ctx, WL_EINVAL,
-                    "partial sums need %zu bytes, above the %zu-byte scratch of the "
-                    "allocation-free evaluation", need, (size_t)WL_NOALLOC_SCRATCH_BYTES);
-      main_out = (double*)ctx->d_noalloc;
-    } else {
-      int rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "partial sums");
-      if (rc) return rc;
-      main_out = (double*)ctx->d_partial;
-    }
+  const size_t need = eval_scratch_bytes(s, ens->n_groups, n_pts);
+  void* buf;
+  if (noalloc) {
+    if (need > WL_NOALLOC_SCRATCH_BYTES)
+      return fail(ctx, WL_EINVAL,
+                  "the evaluation needs %zu bytes of scratch, above the %zu-byte array of "
+                  "the allocation-free evaluation", need, (size_t)WL_NOALLOC_SCRATCH_BYTES);
+    buf = ctx->d_noalloc;
+  } else {
+    int rc = ensure(ctx, &ctx->d_partial, &ctx->partial_bytes, need, "evaluation scratch");
+    if (rc) return rc;
+    buf = ctx->d_partial;
   }
+  const size_t part = (size_t)ens->n_groups * s.n_sub * n_pts;
+  double* p_w = s.n_sub > 1 ? (double*)buf : o.sums;
+  double* p_a = (double*)buf + (s.n_sub > 1 ? part : 0);
+  double* p_v = p_a + part;
+  uint8_t* flags = (uint8_t*)(p_v + part);
+  int32_t* list = (int32_t*)(flags + flag_bytes(n_pts));
   hipError_t e = hipSuccess;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (ctx->timing && !noalloc) {
@@ -641,72 +704,55 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
     if (e == hipSuccess) e = hipEventRecord(ev0, ctx->stream);
   }
   if (e == hipSuccess)
-    e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_seg64, ens->n_ppl, d_rho,
-                           d_T, n_T, n_pts, s, main_out, ctx->stream);
+    e = wl::launch_average(precision, spin, fa, ens->d_seg, ens->d_seg64, ens->d_norm,
+                           ens->n_ppl, d_rho, d_T, n_T, n_pts, s, p_w, p_a, p_v, ctx->stream);
   if (e == hipSuccess && ctx->timing && !noalloc) {
     e = hipEventRecord(ev1, ctx->stream);
     if (e == hipSuccess) ctx->n_timed++;
   }
+  if (e == hipSuccess)
+    e = wl::launch_scale_escalate(precision, spin, fa, ens->d_x, ens->d_y, ens->n_ppl, d_rho,
+                                  d_T, n_T, n_pts, s, ens->n_loops, p_a, p_v, o.scale,
+                                  o.fp_err, flags, list, p_w, ctx->stream);
   if (e == hipSuccess && s.n_sub > 1)
-    e = wl::launch_reduce_sub(main_out, ens->n_groups, s.n_sub, n_pts, d_sums, ctx->stream);
-  if (e == hipSuccess && (d_mean || d_err))
-    e = wl::launch_stats(d_sums, ens->n_groups, n_pts, ens->n_loops, d_mean, d_err,
+    e = wl::launch_reduce_sub(p_w, ens->n_groups, s.n_sub, n_pts, o.sums, ctx->stream);
+  if (e == hipSuccess && (o.mean || o.err))
+    e = wl::launch_stats(o.sums, ens->n_groups, n_pts, ens->n_loops, o.mean, o.err,
                          ctx->stream);
+  if (e == hipSuccess && o.escalated)
+    e = hipMemcpyAsync(o.escalated, flags, n_pts, hipMemcpyDeviceToDevice, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch");
   return WL_OK;
 }
 
-static int average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
-                         const double* d_rho, int32_t n_rho, const double* d_T,
-                         int32_t n_T, int32_t spin, int32_t precision,
-                         double* d_mean, double* d_err, double* d_group_sums,
-                         bool noalloc) {
+static int average_impl(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                        const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+                        int32_t spin, int32_t precision, int32_t flags, const wl_result* out,
+                        bool noalloc) {
   if (!ctx) return WL_EINVAL;
   ctx->err.clear();
+  if (!out) return fail(ctx, WL_EINVAL, "result is NULL");
+  if (flags != WL_HOST_PTR && flags != WL_DEVICE_PTR)
+    return fail(ctx, WL_EINVAL, "unknown flags %d", flags);
   int rc = check_common(ctx, ens, spin, precision);
   if (rc) return rc;
   wl::FieldArgs fa;
   if ((rc = check_field(ctx, field, &fa))) return rc;
-  if (n_rho < 0 || n_T < 0) return fail(ctx, WL_EINVAL, "negative grid size");
-  if ((int64_t)n_rho * n_T > (int64_t)INT32_MAX)
-    return fail(ctx, WL_EINVAL, "grid has more than 2^31-1 points");
-  if ((int64_t)n_rho * n_T == 0) return WL_OK;
-  if (!d_rho || !d_T || !d_group_sums)
-    return fail(ctx, WL_EINVAL, "device pointer is NULL");
-  if (noalloc && !ctx->d_noalloc)
-    return hip_fail(ctx, ctx->noalloc_status, "address of the allocation-free scratch");
-  DeviceGuard g(ctx->device);
-  if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  return average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
-                        d_err, d_group_sums, noalloc);
-}
-
-int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
-                     const double* d_rho, int32_t n_rho, const double* d_T,
-                     int32_t n_T, int32_t spin, int32_t precision,
-                     double* d_mean, double* d_err, double* d_group_sums) {
-  return average_async(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
-                       d_err, d_group_sums, false);
-}
-
-int wl_average_async_noalloc(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
-                             const double* d_rho, int32_t n_rho, const double* d_T,
-                             int32_t n_T, int32_t spin, int32_t precision,
-                             double* d_mean, double* d_err, double* d_group_sums) {
-  return average_async(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
-                       d_err, d_group_sums, true);
-}
-
-int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
-               const double* rho, int32_t n_rho, const double* T, int32_t n_T,
-               int32_t spin, int32_t precision, double* mean, double* err,
-               double* group_sums) {
-  if (!ctx) return WL_EINVAL;
-  ctx->err.clear();
-  int rc = check_common(ctx, ens, spin, precision);
-  if (rc) return rc;
-  wl::FieldArgs fa;
-  if ((rc = check_field(ctx, field, &fa))) return rc;
+  if (flags == WL_DEVICE_PTR) {
+    if (n_rho < 0 || n_T < 0) return fail(ctx, WL_EINVAL, "negative grid size");
+    if ((int64_t)n_rho * n_T > (int64_t)INT32_MAX)
+      return fail(ctx, WL_EINVAL, "grid has more than 2^31-1 points");
+    if ((int64_t)n_rho * n_T == 0) return WL_OK;
+    if (!rho || !T || !out->group_sums)
+      return fail(ctx, WL_EINVAL, "device pointer is NULL");
+    if (noalloc && !ctx->d_noalloc)
+      return hip_fail(ctx, ctx->noalloc_status, "address of the allocation-free scratch");
+    DeviceGuard g(ctx->device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    const DevOut o{out->group_sums, out->mean, out->err, out->scale, out->fp_err,
+                   out->escalated};
+    return average_device(ctx, ens, fa, rho, n_rho, T, n_T, spin, precision, o, noalloc);
+  }
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
   const int64_t n_pts = (int64_t)n_rho * n_T;
   if (n_pts == 0) return WL_OK;
@@ -714,34 +760,76 @@ int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
   const size_t gbytes = (size_t)(n_rho + n_T) * sizeof(double);
   const size_t sums_n = (size_t)ens->n_groups * n_pts;
-  const size_t obytes = (sums_n + 2 * (size_t)n_pts) * sizeof(double);
+  // [group sums | mean | err | scale | fp_err | escalation flags]
+  const size_t obytes = (sums_n + 4 * (size_t)n_pts) * sizeof(double) + (size_t)n_pts;
   if ((rc = ensure(ctx, &ctx->d_grid, &ctx->grid_bytes, gbytes, "grid"))) return rc;
   if ((rc = ensure(ctx, &ctx->d_out, &ctx->out_bytes, obytes, "results"))) return rc;
   double* d_rho = (double*)ctx->d_grid;
   double* d_T = d_rho + n_rho;
-  double* d_sums = (double*)ctx->d_out;
-  double* d_mean = d_sums + sums_n;
-  double* d_err = d_mean + n_pts;
+  DevOut o;
+  o.sums = (double*)ctx->d_out;
+  o.mean = o.sums + sums_n;
+  o.err = o.mean + n_pts;
+  o.scale = o.err + n_pts;
+  o.fp_err = o.scale + n_pts;
+  o.escalated = (uint8_t*)(o.fp_err + n_pts);
   hipError_t e = hipMemcpyAsync(d_rho, rho, n_rho * sizeof(double), hipMemcpyHostToDevice,
                                 ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "grid upload");
-  if ((rc = average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, d_mean,
-                           d_err, d_sums)))
+  if ((rc = average_device(ctx, ens, fa, d_rho, n_rho, d_T, n_T, spin, precision, o)))
     return rc;
-  if (group_sums)
-    e = hipMemcpyAsync(group_sums, d_sums, sums_n * sizeof(double), hipMemcpyDeviceToHost,
-                       ctx->stream);
-  if (e == hipSuccess && mean)
-    e = hipMemcpyAsync(mean, d_mean, n_pts * sizeof(double), hipMemcpyDeviceToHost,
-                       ctx->stream);
-  if (e == hipSuccess && err)
-    e = hipMemcpyAsync(err, d_err, n_pts * sizeof(double), hipMemcpyDeviceToHost,
-                       ctx->stream);
+  const struct {
+    void* host;
+    const void* dev;
+    size_t bytes;
+  } copies[] = {{out->group_sums, o.sums, sums_n * sizeof(double)},
+                {out->mean, o.mean, n_pts * sizeof(double)},
+                {out->err, o.err, n_pts * sizeof(double)},
+                {out->scale, o.scale, n_pts * sizeof(double)},
+                {out->fp_err, o.fp_err, n_pts * sizeof(double)},
+                {out->escalated, o.escalated, (size_t)n_pts}};
+  for (const auto& c : copies)
+    if (e == hipSuccess && c.host)
+      e = hipMemcpyAsync(c.host, c.dev, c.bytes, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "wl_average");
   return WL_OK;
+}
+
+int wl_average_ex(wl_ctx* ctx, const wl_ens* ens, const wl_field* field, const double* rho,
+                  int32_t n_rho, const double* T, int32_t n_T, int32_t spin,
+                  int32_t precision, int32_t flags, const wl_result* out) {
+  return average_impl(ctx, ens, field, rho, n_rho, T, n_T, spin, precision, flags, out,
+                      false);
+}
+
+int wl_average_async(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                     const double* d_rho, int32_t n_rho, const double* d_T,
+                     int32_t n_T, int32_t spin, int32_t precision,
+                     double* d_mean, double* d_err, double* d_group_sums) {
+  const wl_result r{d_mean, d_err, d_group_sums, nullptr, nullptr, nullptr};
+  return average_impl(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision,
+                      WL_DEVICE_PTR, &r, false);
+}
+
+int wl_average_async_noalloc(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+                             const double* d_rho, int32_t n_rho, const double* d_T,
+                             int32_t n_T, int32_t spin, int32_t precision,
+                             double* d_mean, double* d_err, double* d_group_sums) {
+  const wl_result r{d_mean, d_err, d_group_sums, nullptr, nullptr, nullptr};
+  return average_impl(ctx, ens, field, d_rho, n_rho, d_T, n_T, spin, precision,
+                      WL_DEVICE_PTR, &r, true);
+}
+
+int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
+               const double* rho, int32_t n_rho, const double* T, int32_t n_T,
+               int32_t spin, int32_t precision, double* mean, double* err,
+               double* group_sums) {
+  const wl_result r{mean, err, group_sums, nullptr, nullptr, nullptr};
+  return average_impl(ctx, ens, field, rho, n_rho, T, n_T, spin, precision, WL_HOST_PTR, &r,
+                      false);
 }
 
 int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
@@ -797,10 +885,11 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
     hipError_t e = hipMemcpyAsync(d_in, h_in.data(), lay.in_bytes, hipMemcpyHostToDevice,
                                   ctx->stream);
     if (e == hipSuccess)
-      e = wl::launch_batch(prec, ens->d_seg, ens->d_seg64, ens->n_ppl, d_in, ens->n_groups,
-                           ens->n_loops, ctx->d_counter, d_res,
-                           (int32_t)(want_wg < max_wg ? want_wg : max_wg), ctx->stream);
-    std::vector<double> h_res((size_t)(lay.sums_n + 2 * lay.pts_n));
+      e = wl::launch_batch(prec, ens->d_seg, ens->d_seg64, ens->d_norm, ens->d_x, ens->d_y,
+                           ens->n_ppl, d_in, ens->n_groups, ens->n_loops, ctx->d_counter,
+                           d_res, (int32_t)(want_wg < max_wg ? want_wg : max_wg),
+                           ctx->stream);
+    std::vector<double> h_res(lay.head_bytes / sizeof(double));
     if (e == hipSuccess)
       e = hipMemcpyAsync(h_res.data(), d_res, h_res.size() * sizeof(double),
                          hipMemcpyDeviceToHost, ctx->stream);
@@ -885,7 +974,7 @@ int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
   DeviceGuard g(ctx->device);
   if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-  const wl::SubLoop sl{0, ens->n_ppl};
+  const wl::SubLoop sl{0, ens->n_ppl, 0, 1};
   if (precision == WL_FP64 && (rc = need_seg64(ctx, ens))) return rc;
   return per_loop_impl(ctx, ens, fa, ens->d_seg, ens->d_seg64, sl, rho, n_rho, T, n_T, spin,
                        precision, loop0, n_loops, phase, spin_exp, w);
@@ -906,9 +995,9 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   const int32_t h = ens->n_ppl / 2, q = ens->n_ppl / 4;
   wl::SubLoop sl;
   switch (subloop) {
-    case WL_SUB_CIRCLE: sl = wl::SubLoop{0, h}; break;
-    case WL_SUB_SQUARE: sl = wl::SubLoop{h, q}; break;
-    case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q}; break;
+    case WL_SUB_CIRCLE: sl = wl::SubLoop{0, h, 0, 2}; break;
+    case WL_SUB_SQUARE: sl = wl::SubLoop{h, q, 1, 4}; break;
+    case WL_SUB_TRIANGLE: sl = wl::SubLoop{h + q, q, 3, 4}; break;
     default: return fail(ctx, WL_EINVAL, "unknown sub-loop %d", subloop);
   }
   if (loop0 < 0 || n_loops < 0 || loop0 + n_loops > ens->n_loops)
@@ -950,7 +1039,7 @@ static int per_loop_impl(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& fa
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_T, T, n_T * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = wl::launch_per_loop(precision, spin, fa, seg, seg64, ens->n_ppl, sl,
+    e = wl::launch_per_loop(precision, spin, fa, seg, seg64, ens->d_x, ens->d_y, ens->n_ppl, sl,
                             d_rho, d_T, n_T, (int32_t)n_pts, loop0, n_loops, d_ph, d_sp, d_w,
                             ctx->stream);
   if (e == hipSuccess && phase)

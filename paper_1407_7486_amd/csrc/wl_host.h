@@ -27,7 +27,7 @@ struct wl_ctx {
   int* d_flag = nullptr;
   void* d_batch = nullptr;  // batched evaluation: descriptors, grids, results
   size_t batch_bytes = 0;
-  unsigned int* d_counter = nullptr;  // work counter of persistent launches
+  unsigned int* d_counter = nullptr;  // two work counters of persistent launches
   // device address of the allocation-free entry point's static scratch
   // array on this context's device (nullptr if it could not be obtained;
   // noalloc_status then holds the HIP error)
@@ -48,6 +48,7 @@ struct wl_ens {
   float* d_x = nullptr;
   float* d_y = nullptr;
   float4* d_seg = nullptr;
+  float2* d_norm = nullptr;  // per loop: sqrt(sum c^2), sqrt(sum d_y^2)
   // sub-loop segment array of the discretisation estimate, derived on first
   // use by an FP32 discretisation or sub-loop call (same size as d_seg)
   mutable float4* d_sub = nullptr;
@@ -99,19 +100,22 @@ ReqPlan plan_request(const wl_ctx* ctx, const wl_ens* ens, const wl_request& q);
 // Lays out a batch of n requests (all of one precision, none empty).
 // Host staging `h_in` receives [BatchHeader | descriptors @ kBatchDescOffset
 // | grids]; the device copy of it lives at d_in.  Results on the device, at
-// d_res: [group sums | means | errors | sub-range partials].  Returns false
-// if the capacities are exceeded.
+// d_res: the head [group sums | means | errors | scales | rounding
+// estimates | escalation flags (one byte per point, padded to 8)], copied
+// back to the host, then the item scale and rounding accumulators, the
+// sub-range partials, the compacted lists of flagged points and their
+// counts.  Returns false if the capacities are exceeded.
 struct BatchLayout {
-  int64_t items = 0, sums_n = 0, pts_n = 0, part_n = 0;
-  size_t in_bytes = 0, res_bytes = 0;
+  int64_t items = 0, sums_n = 0, pts_n = 0, part_n = 0, acc_n = 0;
+  size_t in_bytes = 0, res_bytes = 0, head_bytes = 0;
   std::vector<int64_t> sums_begin, pts_begin;  // per request
 };
 bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldArgs* fa,
                  const ReqPlan* plans, int32_t n, void* h_in, size_t cap_in, void* d_in,
                  void* d_res, size_t cap_res, BatchLayout* out);
 
-// Copies request i's results out of the host copy of the result region
-// (its first sums_n + 2 pts_n doubles).
+// Copies request i's results out of the host copy of the result region's
+// head (head_bytes).
 void scatter_results(const wl_request& q, const BatchLayout& lay, int32_t i,
                      const double* h_res, int64_t n_groups);
 

@@ -32,9 +32,12 @@ struct Sched {
 
 // Which part of each loop a per-loop evaluation walks: segments seg_off ..
 // seg_off+m-1 of the loop's N entries in the segment array passed (the
-// whole-loop array, or the sub-loop one for a sub-loop).  Whole loop: {0, N}.
+// whole-loop array, or the sub-loop one for a sub-loop), running through the
+// loop's points first, first + stride, ... (mod N).  Whole loop:
+// {0, N, 0, 1}; sub-loops: circle {0, N/2, 0, 2}, square {N/2, N/4, 1, 4},
+// triangle {3N/4, N/4, 3, 4}.
 struct SubLoop {
-  int32_t seg_off, m;
+  int32_t seg_off, m, first, stride;
 };
 
 // Field constants prepared on the host for one launch.
@@ -72,6 +75,13 @@ struct ReqDesc {
   const double* T;
   double* out;          // item outputs: partial [G*n_sub][n_pts], or the
                         // group sums directly when n_sub == 1
+  double* out_a;        // [G*n_sub][n_pts] scale and rounding accumulators
+  double* out_v;        //   of the items (always partial rows)
+  double* scale;        // [n_pts] scale M_S of each mean
+  double* fp_err;       // [n_pts] rounding-error estimate of each mean
+  uint8_t* flags;       // [n_pts] grid points recomputed in FP64
+  int32_t* list;        // [n_pts] the flagged points, compacted
+  int32_t* count;       // [1] how many are flagged
   int64_t item_begin;   // first item of this request in the batch
   int64_t loops_per_sub;
   int64_t sums_begin;   // offset of [G][n_pts] group sums in the batch
@@ -89,8 +99,10 @@ constexpr int kWave = 64;
 
 // Launchers (wl_kernels.hip).  All enqueue on `stream` and return the HIP
 // launch status.
+// Segment array d_seg of every loop (flags non-finite input in *d_bad) and
+// the loop norms d_norm [n_loops] (sqrt(sum c^2), sqrt(sum d_y^2)).
 hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
-                       int32_t n_ppl, float4* d_seg, int* d_bad,
+                       int32_t n_ppl, float4* d_seg, float2* d_norm, int* d_bad,
                        hipStream_t stream);
 
 // d-loop generation (Sec. 2.1) into d_x, d_y [n_loops][n_ppl] (n_ppl a
@@ -104,18 +116,34 @@ hipError_t launch_generate(uint64_t seed, int64_t first_loop, int64_t n_loops, i
 hipError_t launch_prep64(const float* d_x, const float* d_y, int64_t n_loops,
                          int32_t n_ppl, double4* d_seg64, hipStream_t stream);
 
-// d_seg (FP32 paths) or d_seg64 (FP64) must be set for the precision asked.
+// One evaluation's main kernel: item partial sums of w into d_out, of the
+// scale and rounding accumulators into d_out_a, d_out_v (all [G*n_sub]
+// [n_pts]; d_out is the group sums when n_sub == 1).  d_seg (FP32 paths) or
+// d_seg64 (FP64) must be set for the precision asked.
 hipError_t launch_average(int precision, int spin, const FieldArgs& f,
-                          const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
-                          const double* d_rho, const double* d_T, int32_t n_T,
-                          int32_t n_pts, const Sched& s, double* d_out,
-                          hipStream_t stream);
+                          const float4* d_seg, const double4* d_seg64, const float2* d_norm,
+                          int32_t n_ppl, const double* d_rho, const double* d_T,
+                          int32_t n_T, int32_t n_pts, const Sched& s, double* d_out,
+                          double* d_out_a, double* d_out_v, hipStream_t stream);
+
+// Per grid point from d_out_a, d_out_v: the scale (M_S), the rounding-error
+// estimate of the mean and the FP64 recomputation flag (scale and fp_err
+// may be NULL).  Then, for WL_FP32C, the flagged points compacted into
+// d_list [n_pts + 1] (the last entry their count) and the FP64 recomputation
+// of their item sums in d_out from the raw points d_x, d_y.
+hipError_t launch_scale_escalate(int precision, int spin, const FieldArgs& f,
+                                 const float* d_x, const float* d_y, int32_t n_ppl,
+                                 const double* d_rho, const double* d_T, int32_t n_T,
+                                 int32_t n_pts, const Sched& s, int64_t n_loops,
+                                 const double* d_out_a, const double* d_out_v,
+                                 double* d_scale, double* d_fp_err, uint8_t* d_flags,
+                                 int32_t* d_list, double* d_out, hipStream_t stream);
 
 // The segment array of the precision asked must be set: d_seg (FP32 paths)
 // or d_seg64 (FP64), whole-loop or sub-loop layout as `sl` says.
 hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
-                           const float4* d_seg, const double4* d_seg64, int32_t n_ppl,
-                           const SubLoop& sl,
+                           const float4* d_seg, const double4* d_seg64, const float* d_x,
+                           const float* d_y, int32_t n_ppl, const SubLoop& sl,
                            const double* d_rho, const double* d_T,
                            int32_t n_T, int32_t n_pts, int64_t loop0,
                            int64_t n_loops, double* d_phase, double* d_spin,
@@ -149,12 +177,16 @@ hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
                               int64_t n_loops, double* d_mean, double* d_err,
                               double* d_delta, hipStream_t stream);
 
-// Batched evaluation: counter reset, persistent item kernel, sub-range
-// reduction and statistics, all reading `d_hdr` (BatchHeader followed by
-// the descriptors).  Results at d_res: [group sums | means | errors |
-// partials] with the sizes from the header.  Grid sizes are fixed (n_wg
-// persistent workgroups), so the sequence can be captured once and replayed.
+// Batched evaluation: counter reset, persistent item kernel, scale and
+// escalation flags, (WL_FP32C) persistent FP64 recomputation of the flagged
+// points, sub-range reduction and statistics, all reading `d_hdr`
+// (BatchHeader followed by the descriptors, whose pointers place every
+// array).  Results at d_res: [group sums | means | errors | scales |
+// rounding estimates | flags | ...] with the sizes from the header.  Grid
+// sizes are fixed (n_wg persistent workgroups) and d_counter holds two
+// work counters, so the sequence can be captured once and replayed.
 hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg64,
+                        const float2* d_norm, const float* d_x, const float* d_y,
                         int32_t n_ppl, const void* d_hdr, int32_t n_groups, int64_t n_loops,
                         unsigned int* d_counter, double* d_res, int32_t n_wg,
                         hipStream_t stream);

@@ -113,9 +113,9 @@ hipError_t capture(wl_server* s, Slot* sl, int prec) {
   hipError_t r = hipMemcpyAsync(sl->d_in, sl->h_in, s->cfg.input_bytes, hipMemcpyHostToDevice,
                                 sl->stream);
   if (r == hipSuccess)
-    r = wl::launch_batch(prec, e->d_seg, e->d_seg64, e->n_ppl, sl->d_in, e->n_groups,
-                         e->n_loops, sl->d_counter, (double*)sl->d_res, persistent_wgs(s),
-                         sl->stream);
+    r = wl::launch_batch(prec, e->d_seg, e->d_seg64, e->d_norm, e->d_x, e->d_y, e->n_ppl,
+                         sl->d_in, e->n_groups, e->n_loops, sl->d_counter,
+                         (double*)sl->d_res, persistent_wgs(s), sl->stream);
   hipGraph_t g = nullptr;
   st = hipStreamEndCapture(sl->stream, &g);
   if (r != hipSuccess) {
@@ -182,7 +182,7 @@ hipError_t launch_slot(wl_server* s, Slot* sl) {
   hipError_t e = hipSuccess;
   if (!sl->exec[sl->prec]) e = capture(s, sl, sl->prec);
   if (e == hipSuccess) e = hipGraphLaunch(sl->exec[sl->prec], sl->stream);
-  const size_t out_b = 8 * (size_t)(sl->lay.sums_n + 2 * sl->lay.pts_n);
+  const size_t out_b = sl->lay.head_bytes;
   if (e == hipSuccess)
     e = hipMemcpyAsync(sl->h_res, sl->d_res, out_b, hipMemcpyDeviceToHost, sl->stream);
   sl->done.store(false, std::memory_order_relaxed);
@@ -284,7 +284,7 @@ int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl->h_res, c.result_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&sl->d_in, c.input_bytes);
     if (e == hipSuccess) e = hipMalloc(&sl->d_res, c.result_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl->d_counter, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMalloc((void**)&sl->d_counter, 2 * sizeof(unsigned int));
     s->slots.push_back(std::move(sl));
     if (e != hipSuccess) {
       wl_server* raw = s.release();

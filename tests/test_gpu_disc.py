@@ -144,14 +144,21 @@ def test_levels_small(wl, ctx, small, fname, spin, pname, mode):
 def test_full_mode_level_n_is_the_average(wl, ctx, small, spin, pname):
     """Full-loop mode's level N is the whole loop's w as wl_average computes
     it: the same group sums and means, bit for bit (same kernels' segment
-    arithmetic, same loop order and sub-range split)."""
+    arithmetic, same loop order and sub-range split), at every grid point
+    the average did not recompute in FP64.  (The discretisation estimate has
+    no FP64 guard: at the recomputed points its FP32 level stays within the
+    FP32 rounding estimate, the stated one times 2^29, of the average.)"""
     x, y, ens = small
     say("full-mode level N vs average", "spin", spin, pname)
     fld = wl.field(1, 1.3, 0.7)
     mean, _, _, sums = wl.wl_discretisation(ctx, ens, fld, RHO, TGRID, spin, PRECS[pname], 1)
-    m1, _, s1 = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, PRECS[pname])
-    assert np.array_equal(sums[0], s1)
-    assert np.array_equal(mean[0], m1)
+    r = wl.wl_average_ex(ctx, ens, fld, RHO, TGRID, spin, PRECS[pname])
+    keep = r["escalated"] == 0
+    say("points recomputed in FP64 by the average:", int((~keep).sum()), "of", keep.size)
+    assert np.array_equal(sums[0][:, keep], r["group_sums"][:, keep])
+    assert np.array_equal(mean[0][keep], r["mean"][keep])
+    esc = ~keep
+    assert (np.abs(mean[0][esc] - r["mean"][esc]) <= r["fp_err"][esc] * 2.0 ** 29).all()
 
 
 @pytest.mark.parametrize("spin", [0, 1])

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import wlinputs
-from wl_tol import check_means, check_per_loop, mean_scales
+from wl_tol import check_fp_err, check_means, check_per_loop, mean_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -75,12 +75,18 @@ def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
     ph, sp, w = wl.wl_per_loop(ctx, ens, fld, RHO, TGRID, spin, prec, 0, 128)
     r1 = check_per_loop(prec, ph, sp, w, o["phase"], o["spin"], o["w"], spin,
                         o["phase_sq"], o["phase_abs"])
-    mean, err, sums = wl.wl_average(ctx, ens, fld, RHO, TGRID, spin, prec)
+    r = wl.wl_average_ex(ctx, ens, fld, RHO, TGRID, spin, prec)
+    mean, err, sums = r["mean"], r["err"], r["group_sums"]
     o_mean, o_err, _ = oracle.stats(o["group_sums"], 128)
-    r2 = check_means(prec, mean, sums, o_mean, o["group_sums"],
-                     *mean_scales(o["w"], o["spin"], 4))
-    say("worst error/tolerance: phase %.3g spin %.3g w %.3g mean %.3g sums %.3g"
-        % (*r1, *r2))
+    m_s, g_s = mean_scales(o["w"], o["spin"], 4, spin)
+    r2 = check_means(prec, mean, sums, o_mean, o["group_sums"], m_s, g_s)
+    # the scale of each mean, and (compensated FP32) the stated rounding
+    # estimate bounds the actual error
+    np.testing.assert_allclose(r["scale"], m_s, rtol=1e-12 if prec == 2 else 1e-3)
+    r3 = check_fp_err(mean, o_mean, r["fp_err"], r["escalated"], m_s) if prec == 0 else 0.0
+    assert set(np.unique(r["escalated"])) <= ({0, 1} if prec == 0 else {0})
+    say("worst error/tolerance: phase %.3g spin %.3g w %.3g mean %.3g sums %.3g; "
+        "mean error / stated estimate %.3g" % (*r1, *r2, r3))
     # the group error follows from the group sums the same way on both sides
     _, e2, _ = oracle.stats(sums, 128)
     np.testing.assert_allclose(err, e2, rtol=1e-9, atol=1e-300)
@@ -108,7 +114,7 @@ def test_narrow_and_wide_tubes(wl, ctx, small, lam, pname):
         mean, _, sums = wl.wl_average(ctx, ens, fld, rho, T, 1, prec)
         o_mean, _, _ = oracle.stats(o["group_sums"], 128)
         check_means(prec, mean, sums, o_mean, o["group_sums"],
-                    *mean_scales(o["w"], o["spin"], 4))
+                    *mean_scales(o["w"], o["spin"], 4, 1))
 
 
 def test_subrange_and_ragged_loop_window(wl, ctx, small):
@@ -279,20 +285,20 @@ def test_batch_equals_alone(wl, ctx):
                              precision=(0, 2, 1)[i % 3]))
         reqs.append(dict(kind=1, eB0=1.0, lam=1.0, rho=np.zeros(0), T=TGRID, spin=1,
                          precision=0))
-        outs = wl.wl_average_batch(ctx, ens, reqs)
-        for q, (m, e, s_) in zip(reqs, outs):
+        outs = wl.wl_average_batch(ctx, ens, reqs, full=True)
+        for q, ob in zip(reqs, outs):
             if q["rho"].size == 0:
                 continue
-            m1, e1, s1 = wl.wl_average(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
-                                       q["rho"], q["T"], q["spin"], q["precision"])
-            assert np.array_equal(s_, s1), q
-            assert np.array_equal(m, m1) and np.array_equal(e, e1, equal_nan=True)
+            o1 = wl.wl_average_ex(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
+                                  q["rho"], q["T"], q["spin"], q["precision"])
+            for k in wl.RESULT_KEYS:
+                assert np.array_equal(ob[k], o1[k], equal_nan=True), (k, q)
         q = reqs[5]
         o = oracle.evaluate(x, y, q["kind"], q["eB0"], q["lam"], q["rho"], q["T"], q["spin"],
                             8, per_loop=True)
         o_mean, _, _ = oracle.stats(o["group_sums"], 256)
-        check_means(q["precision"], outs[5][0], outs[5][2], o_mean, o["group_sums"],
-                    *mean_scales(o["w"], o["spin"], 8))
+        check_means(q["precision"], outs[5]["mean"], outs[5]["group_sums"], o_mean,
+                    o["group_sums"], *mean_scales(o["w"], o["spin"], 8, q["spin"]))
     finally:
         wl.wl_ensemble_free(ens)
 
@@ -320,11 +326,11 @@ def test_server_results_equal_alone(wl, ctx):
             info = srv.info()
             assert info["batches"] >= 5 and info["pending"] == 0
             for q, t in zip(reqs, tickets):
-                m, e, s_ = srv.result(t)
-                m1, e1, s1 = wl.wl_average(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
-                                           q["rho"], q["T"], q["spin"], q["precision"])
-                assert np.array_equal(s_, s1) and np.array_equal(m, m1)
-                assert np.array_equal(e, e1, equal_nan=True)
+                ob = srv.result(t, full=True)
+                o1 = wl.wl_average_ex(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
+                                      q["rho"], q["T"], q["spin"], q["precision"])
+                for k in wl.RESULT_KEYS:
+                    assert np.array_equal(ob[k], o1[k], equal_nan=True), (k, q)
             big = dict(kind=1, eB0=1.0, lam=1.0, rho=np.linspace(0, 3, 128),
                        T=np.geomspace(1e-3, 10, 64), spin=1, precision=0)
             with pytest.raises(wl.WLError) as ei:
@@ -356,7 +362,7 @@ def test_constant_field_workload_against_closed_forms(wl, ctx):
         for prec in (2, 0):
             m, e, s_ = wl.wl_average(ctx, ens, wl.field(0, 1.0), rho, T, 0, prec)
             check_means(prec, m, s_, o_mean, o["group_sums"],
-                        *mean_scales(o["w"], o["spin"], cfg["n_groups"]))
+                        *mean_scales(o["w"], o["spin"], cfg["n_groups"], 0))
             assert np.all(np.abs(m - wn) <= 5 * e + 1e-12)
         cont = oracle.w_scalar_continuum(T)
         assert np.all(np.abs(np.log(wn / cont) - T ** 2 / (2 * cfg["n_ppl"])) < 1e-3)

@@ -1,10 +1,18 @@
 """Precision stress: FP32 plain vs FP32 compensated vs FP64 against the
 oracle, on the first 1024 loops (8192 points) of the 131072-loop ensemble,
 for sech^2 tubes B0 in {1, 5, 20} x lambda in {0.25, 1, 4}, 32 rho_cm in
-[0, 5] and 48 T up to eB0*T = 200, scalar and spinor.  The oracle runs on an
-8 x 12 sub-grid (every 4th rho and T; WL_STRESS_STRIDE=1 in the environment
-takes the whole 32 x 48 grid, ~11 minutes of oracle time on 16 threads).
-Prints the error table."""
+[0, 5] and 48 T up to eB0*T = 200, scalar and spinor.  The wide tubes
+(lambda = 4, where the phase sums cancel most) run on the whole 32 x 48 grid;
+the others on an 8 x 12 sub-grid (every 4th rho and T; WL_STRESS_STRIDE=1 in
+the environment takes the whole grid for every field, ~11 minutes of oracle
+time on 16 threads).  The oracle runs once per field (spinor): the scalar
+case has the same phases, w = cos(Phi).
+
+Compensated FP32 must meet the stated bars with no conditioning terms:
+per-loop phase 1e-5 max(1, |Phi|), spin exponent 1e-5 max(1, S), means
+1e-6 M_S, and each mean's error within the library's own rounding
+estimate.  Prints the error table, with the share of per-loop values and of
+grid points the library recomputed in FP64."""
 import os
 import sys
 
@@ -13,7 +21,7 @@ import pytest
 
 import oracle
 import wlinputs
-from wl_tol import TOL, mean_random_scale, mean_scales, phase_limit
+from wl_tol import TOL, U64, check_fp_err, mean_scales, phase_limit
 
 pytestmark = pytest.mark.gpu
 
@@ -32,50 +40,78 @@ def setup():
     wl.wl_destroy(ctx)
 
 
+def group_sums(w):
+    return w.reshape(G, N_LOOPS // G, *w.shape[1:]).sum(axis=1)
+
+
 def test_precision_stress_table(setup):
     wl, ctx, ens, x, y = setup
     rows = []
-    worst = {0: 0.0, 2: 0.0}
+    worst = {"fp32c_mean": 0.0, "fp32c_fperr": 0.0, "fp64_mean": 0.0}
     for fcfg in wlinputs.stress_fields():
-        rho = wlinputs.rho_grid(*fcfg["rho"])[::STRIDE]
-        T = wlinputs.t_grid(*fcfg["T"])[::STRIDE]
+        stride = 1 if fcfg["lam"] == 4.0 else STRIDE
+        rho = wlinputs.rho_grid(*fcfg["rho"])[::stride]
+        T = wlinputs.t_grid(*fcfg["T"])[::stride]
+        print(f"[case] stress oracle B0={fcfg['eB0']} lam={fcfg['lam']} "
+              f"grid {rho.size}x{T.size}", flush=True)
+        o1 = oracle.evaluate(x, y, 1, fcfg["eB0"], fcfg["lam"], rho, T, 1, G, per_loop=True)
+        fld = wl.field(1, fcfg["eB0"], fcfg["lam"])
         for spin in (0, 1):
             print(f"[case] stress B0={fcfg['eB0']} lam={fcfg['lam']} spin={spin}", flush=True)
-            o = oracle.evaluate(x, y, 1, fcfg["eB0"], fcfg["lam"], rho, T, spin, G,
-                                per_loop=True)
-            o_mean, _, _ = oracle.stats(o["group_sums"], N_LOOPS)
-            m_s, _ = mean_scales(o["w"], o["spin"], G)
-            # random per-loop phase errors carried to the mean (5 sigma at a
-            # per-loop relative phase error of the mean tolerance's size)
-            m_r, _ = mean_random_scale(o["phase"], o["spin"], spin, G)
-            fld = wl.field(1, fcfg["eB0"], fcfg["lam"])
+            o_ph = o1["phase"]
+            o_sp = o1["spin"] if spin else np.zeros_like(o1["spin"])
+            o_w = o1["w"] if spin else np.cos(o_ph)
+            o_mean = group_sums(o_w).sum(axis=0) / N_LOOPS
+            m_s, _ = mean_scales(o_w, o_sp, G, spin)
             row = [fcfg["eB0"], fcfg["lam"], spin]
+            res = {}
             for prec in (1, 0, 2):  # plain FP32, FP32C, FP64
                 ph, sp, w = wl.wl_per_loop(ctx, ens, fld, rho, T, spin, prec, 0, N_LOOPS)
-                mean, _, _ = wl.wl_average(ctx, ens, fld, rho, T, spin, prec)
-                dph = np.abs(ph - o["phase"])
-                e_ph = float((dph / np.maximum(1, np.abs(o["phase"]))).max())
-                # share of loops beyond the plain 1e-5 phase tolerance
-                f_ph = float((dph > 1e-5 * np.maximum(1, np.abs(o["phase"]))).mean())
-                e_sp = float((np.abs(sp - o["spin"]) / np.maximum(1, o["spin"])).max()) if spin else 0.0
-                e_m = float((np.abs(mean - o_mean) / m_s).max())
-                row += [e_ph, f_ph, e_sp, e_m]
-                if prec in worst:
-                    lim = TOL[prec]["mean"] * (m_s + 5.0 * m_r)
-                    worst[prec] = max(worst[prec], float((np.abs(mean - o_mean) / lim).max()))
-                    lim = phase_limit(prec, o["phase"], o["phase_sq"], o["phase_abs"])
-                    assert (dph <= lim).all(), (fcfg, spin, prec, float((dph / lim).max()))
+                r = wl.wl_average_ex(ctx, ens, fld, rho, T, spin, prec)
+                res[prec] = (ph, r)
+                dph = np.abs(ph - o_ph)
+                rel = dph / np.maximum(1, np.abs(o_ph))
+                e_sp = float((np.abs(sp - o_sp) / np.maximum(1, o_sp)).max()) if spin else 0.0
+                dm = np.abs(r["mean"] - o_mean)
+                row += [float(rel.max()), float((rel > 1e-5).mean()), e_sp,
+                        float((dm / m_s).max())]
+                if prec == 0:
+                    # the stated bars, no conditioning terms
+                    assert (rel <= 1e-5).all(), (fcfg, spin, float(rel.max()))
+                    if spin:
+                        assert e_sp <= 1e-5, (fcfg, spin, e_sp)
+                    worst["fp32c_mean"] = max(worst["fp32c_mean"], float((dm / m_s).max()))
+                    worst["fp32c_fperr"] = max(worst["fp32c_fperr"],
+                                               check_fp_err(r["mean"], o_mean, r["fp_err"],
+                                                            r["escalated"], m_s))
+                    np.testing.assert_allclose(r["scale"], m_s, rtol=1e-3)
+                elif prec == 2:
+                    lim = phase_limit(2, o_ph, o1["phase_sq"], o1["phase_abs"])
+                    assert (dph <= lim).all(), (fcfg, spin, float((dph / lim).max()))
+                    # both sides round each segment term by a few u: the mean
+                    # inherits sin(Phi) cosh(S) times that, added over loops
+                    ch = np.cosh(o_sp)
+                    rnd = np.sqrt(((np.sin(o_ph) * ch * np.sqrt(o1["phase_sq"])) ** 2)
+                                  .sum(axis=0)) / N_LOOPS
+                    lim_m = TOL[2]["mean"] * m_s + 16 * U64 * rnd
+                    worst["fp64_mean"] = max(worst["fp64_mean"], float((dm / lim_m).max()))
+            # escalated per-loop values equal the FP64 path's bit for bit
+            esc_pl = float((res[0][0] == res[2][0]).mean())
+            esc_pt = float(res[0][1]["escalated"].mean())
+            row += [esc_pl, esc_pt]
             rows.append(row)
     hdr = ("B0", "lam", "spin",
            "fp32:phase", "fp32:>1e-5", "fp32:S", "fp32:mean",
            "fp32c:phase", "fp32c:>1e-5", "fp32c:S", "fp32c:mean",
-           "fp64:phase", "fp64:>1e-5", "fp64:S", "fp64:mean")
+           "fp64:phase", "fp64:>1e-5", "fp64:S", "fp64:mean",
+           "fp32c:esc-loops", "fp32c:esc-points")
     print("\nPRECISION-STRESS TABLE (max relative errors vs the FP64 oracle; mean errors "
-          "relative to M_S = mean |w| max(1,S))")
+          "relative to M_S = mean |w| max(1,S); escalated: shares recomputed in FP64)")
     print(" | ".join(hdr))
     for r in rows:
         print(" | ".join(f"{v:g}" if i < 3 else f"{v:.2e}" for i, v in enumerate(r)))
-    print(f"worst mean error / tolerance (M_S plus 5x the random phase spread): "
-          f"fp32c {worst[0]:.3g}, fp64 {worst[2]:.3g}")
+    print(f"worst: fp32c mean error / 1e-6 M_S {worst['fp32c_mean'] / 1e-6:.3g}, "
+          f"fp32c mean error / stated estimate {worst['fp32c_fperr']:.3g}, "
+          f"fp64 mean error / tolerance {worst['fp64_mean']:.3g}")
     sys.stdout.flush()
-    assert worst[0] <= 1.0 and worst[2] <= 1.0
+    assert worst["fp32c_mean"] <= 1e-6 and worst["fp64_mean"] <= 1.0

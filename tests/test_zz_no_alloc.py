@@ -3,7 +3,7 @@ wl_average_async, through the C ABI: the same kernels and work split, so the
 group sums, means and errors must agree bit for bit (within the FP64 parity
 bar a fortiori).  Two calls in a row, the second with a smaller input, so
 that the second reads a scratch array that still holds the first call's
-partial sums; then the refusals (oversized partial sums, FP64 before the
+item sums and flags; then the refusals (oversized scratch, FP64 before the
 ensemble's FP64 segment array exists) and a valid call after them."""
 import sys
 
@@ -85,11 +85,15 @@ def test_noalloc_refusals_and_fp64(env):
         run(wl, torch, dev, ctx, ens, wl.wl_average_async_noalloc, fld, rho, T, 1,
             wl.WL_FP64)
     assert ei.value.code == wl.WL_EINVAL and "FP64 segment array" in str(ei.value)
-    say("noalloc: partial sums above the scratch size refused before any launch")
-    # 256 x 257 points, 8 groups split 16 ways: 8*16*65792*8 bytes > 64 MiB
+    say("noalloc: scratch above the array's size refused before any launch")
+    # 1500 x 1500 points: too many for a split of the groups' loops, so the
+    # scale and rounding accumulators alone take 2 * 8 * 2.25e6 * 8 bytes,
+    # plus a flag byte per point: above WL_NOALLOC_SCRATCH_BYTES
+    n = 1500
+    assert 2 * 8 * n * n * 8 + n * n > wl.WL_NOALLOC_SCRATCH_BYTES
     with pytest.raises(wl.WLError) as ei:
         run(wl, torch, dev, ctx, ens, wl.wl_average_async_noalloc, fld,
-            np.linspace(0.0, 3.0, 256), np.geomspace(1e-2, 10.0, 257), 0, wl.WL_FP32C)
+            np.linspace(0.0, 3.0, n), np.geomspace(1e-2, 10.0, n), 0, wl.WL_FP32C)
     assert ei.value.code == wl.WL_EINVAL and "scratch" in str(ei.value)
     say("FP64 async (derives the FP64 segment array), then FP64 noalloc")
     ref = run(wl, torch, dev, ctx, ens, wl.wl_average_async, fld, rho, T, 1, wl.WL_FP64)

@@ -78,21 +78,29 @@ def valu_rates():
     import torch
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1407_7486_amd", "libwl_probe.so"))
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    rates = (ctypes.c_double * 3)()
-    ms = (ctypes.c_double * 3)()
+    rates = (ctypes.c_double * 7)()
+    ms = (ctypes.c_double * 7)()
     rc = lib.wl_probe_valu_rates(ctypes.c_int(n_cu), ctypes.c_int(3), rates, ms)
     if rc != 0:
         raise RuntimeError(f"VALU probe failed with HIP error {rc}")
     clock = 2.4e9
     simds = 4 * n_cu
+    # the mixed stream (1 transcendental : 4 FMA) takes, per 5 instructions,
+    # this share of the time its parts take at their separate rates
+    mix_share = (5.0 / rates[3]) / (1.0 / rates[1] + 4.0 / rates[0])
     out = {"n_cu": n_cu, "fp32_fma_wave_insts_per_s": rates[0],
            "trans_wave_insts_per_s": rates[1], "fp64_fma_wave_insts_per_s": rates[2],
+           "mix_wave_insts_per_s": rates[3], "mix_time_over_sum_of_parts": mix_share,
+           "fmac_vop2_wave_insts_per_s": rates[4], "mul_vop2_wave_insts_per_s": rates[5],
+           "add_vop2_wave_insts_per_s": rates[6],
            "ms": list(ms),
            # cycles per wave-instruction per SIMD at the 2.4 GHz peak clock
            "cycles_per_inst_at_2.4GHz": [simds * clock / r for r in rates],
            "fp32_fma_lane_ops_per_s": 64 * rates[0]}
     print(json.dumps(out), flush=True)
-    print(f"rates: fp32={rates[0]:.6e} trans={rates[1]:.6e} fp64={rates[2]:.6e}", flush=True)
+    print(f"rates: fp32={rates[0]:.6e} trans={rates[1]:.6e} fp64={rates[2]:.6e} "
+          f"mix={rates[3]:.6e} fmac={rates[4]:.6e} mul={rates[5]:.6e} add={rates[6]:.6e}",
+          flush=True)
 
 
 def copy_calibration(nbytes):

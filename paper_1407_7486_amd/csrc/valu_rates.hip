@@ -9,6 +9,9 @@
 //   trans  v_rsq_f32, v_exp_f32, v_rcp_f32, v_log_f32 in turn
 //                                        (4 per chain, 32 per iteration)
 //   fp64   v_fma_f64                     (8 per iteration)
+//   mix    1 transcendental + 4 v_fma_f32 per chain (40 per iteration)
+//   vop2   v_fmac_f32, v_mul_f32 or v_add_f32 with VGPR operands (8 per
+//          iteration)
 // The chains' values stay finite or settle on fixed points (the rates do not
 // depend on the operands), and every result feeds one store so that nothing
 // is dead.  Rate = wave-instructions issued over the chip per second.
@@ -34,6 +37,31 @@ __global__ __launch_bounds__(kBlock) void k_rate_fp32(float* __restrict__ out, i
   out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
+// Two-operand (VOP2) forms with a VGPR operand: v_fmac_f32 (MODE 0),
+// v_mul_f32 (1), v_add_f32 (2), 8 per iteration.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_rate_vop2(float* __restrict__ out, int iters,
+                                                      float b, float c) {
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = 1e-3f * (float)(threadIdx.x + j);
+  // lane-varying operands, so that they live in VGPRs
+  const float bv = b + 1e-9f * (float)threadIdx.x;
+  const float cv = c + 1e-9f * (float)threadIdx.x;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (MODE == 0) a[j] = fmaf(bv, cv, a[j]);
+      else if (MODE == 1) a[j] = a[j] * bv;
+      else a[j] = a[j] + cv;
+    }
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += a[j];
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rate_trans(float* __restrict__ out, int iters) {
   float a[8];
 #pragma unroll
@@ -45,6 +73,36 @@ __global__ __launch_bounds__(kBlock) void k_rate_trans(float* __restrict__ out, 
       const float e = __builtin_amdgcn_exp2f(-r);
       const float q = __builtin_amdgcn_rcpf(e);
       a[j] = __builtin_amdgcn_logf(q);
+    }
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s += a[j];
+  out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// Mixed stream: per chain and iteration one transcendental (rsq, exp, rcp
+// and log in turn over four iterations' worth of chains) and 4 FP32 FMAs,
+// the ratio of the evaluation kernel's sech^2 segment (4 transcendentals,
+// ~15 other operations).  If the transcendental unit overlapped the FP32
+// pipe, an iteration would take less than the sum of its parts' times.
+__global__ __launch_bounds__(kBlock) void k_rate_mix(float* __restrict__ out, int iters,
+                                                     float b, float c) {
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = 1.0f + 1e-3f * (float)(threadIdx.x + j);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float t;
+      if (j % 4 == 0) t = __builtin_amdgcn_rsqf(a[j]);
+      else if (j % 4 == 1) t = __builtin_amdgcn_exp2f(-a[j]);
+      else if (j % 4 == 2) t = __builtin_amdgcn_rcpf(a[j]);
+      else t = __builtin_amdgcn_logf(a[j]);
+      t = fmaf(t, b, c);
+      t = fmaf(t, b, c);
+      t = fmaf(t, b, c);
+      a[j] = fmaf(t, b, 1.0f);
     }
   }
   float s = 0.0f;
@@ -72,11 +130,12 @@ __global__ __launch_bounds__(kBlock) void k_rate_fp64(double* __restrict__ out, 
 
 extern "C" {
 
-// Measures the three rates on the current device: rates[0..2] = FP32 FMA,
-// transcendental and FP64 FMA wave-instructions per second over the chip
-// (best of `reps` timed launches each, after one warm-up); ms[0..2] the
-// best launch durations.  n_cu: compute units (8 waves per SIMD are
-// launched on each).  Returns 0, or the HIP error code.
+// Measures the rates on the current device: rates[0..6] = FP32 FMA (VOP3,
+// SGPR operand), transcendental, FP64 FMA, mixed stream (1 transcendental :
+// 4 FMA), v_fmac_f32, v_mul_f32 and v_add_f32 (VOP2) wave-instructions per
+// second over the chip (best of `reps` timed launches each, after one
+// warm-up); ms[0..6] the best launch durations.  n_cu: compute units (8
+// waves per SIMD are launched on each).  Returns 0, or the HIP error code.
 int wl_probe_valu_rates(int n_cu, int reps, double* rates, double* ms) {
   const int64_t n_blocks = (int64_t)n_cu * 4 * 8 * 64 / kBlock;
   const int64_t n_threads = n_blocks * kBlock;
@@ -87,9 +146,9 @@ int wl_probe_valu_rates(int n_cu, int reps, double* rates, double* ms) {
   hipEvent_t t0, t1;
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
-  const int iters[3] = {1 << 18, 1 << 14, 1 << 16};
-  const double per_iter[3] = {8.0, 32.0, 8.0};
-  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+  const int iters[7] = {1 << 18, 1 << 14, 1 << 16, 1 << 15, 1 << 18, 1 << 18, 1 << 18};
+  const double per_iter[7] = {8.0, 32.0, 8.0, 40.0, 8.0, 8.0, 8.0};
+  for (int k = 0; k < 7 && e == hipSuccess; ++k) {
     float best = 1e30f;
     for (int r = -1; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(t0, nullptr);
@@ -99,9 +158,21 @@ int wl_probe_valu_rates(int n_cu, int reps, double* rates, double* ms) {
       else if (k == 1)
         hipLaunchKernelGGL(k_rate_trans, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
                            (float*)buf, iters[1]);
-      else
+      else if (k == 2)
         hipLaunchKernelGGL(k_rate_fp64, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
                            (double*)buf, iters[2], 0.999, 1e-3);
+      else if (k == 3)
+        hipLaunchKernelGGL(k_rate_mix, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
+                           (float*)buf, iters[3], 0.999f, 1e-3f);
+      else if (k == 4)
+        hipLaunchKernelGGL(k_rate_vop2<0>, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
+                           (float*)buf, iters[4], 0.999f, 1e-3f);
+      else if (k == 5)
+        hipLaunchKernelGGL(k_rate_vop2<1>, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
+                           (float*)buf, iters[5], 0.999f, 1e-3f);
+      else
+        hipLaunchKernelGGL(k_rate_vop2<2>, dim3((uint32_t)n_blocks), dim3(kBlock), 0, nullptr,
+                           (float*)buf, iters[6], 0.999f, 1e-3f);
       if (e == hipSuccess) e = hipGetLastError();
       if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
       if (e == hipSuccess) e = hipEventSynchronize(t1);

@@ -230,23 +230,6 @@ __device__ __forceinline__ double4 seg_quantities64(double x0, double y0, double
   return o;
 }
 
-// Segment j of a (sub-)loop of the raw FP32 points, as FP64 quantities:
-// the loop's points first, first + stride, first + 2 stride, ... (indices mod
-// N), so {0, 1} is the whole loop and {0, 2}, {1, 4}, {3, 4} its circle,
-// square and triangle sub-loops.  The same arithmetic as the FP64 segment
-// arrays, so a walk over it gives the FP64 path's sums bit for bit.
-struct RawLoop {
-  const float* __restrict__ x;
-  const float* __restrict__ y;
-  int32_t n_ppl, first, stride;
-  __device__ __forceinline__ double4 operator()(int32_t j) const {
-    const int32_t a = first + stride * j;
-    int32_t b = a + stride;
-    if (b >= n_ppl) b -= n_ppl;
-    return seg_quantities64(x[a], y[a], x[b], y[b]);
-  }
-};
-
 // An FP64 segment array read in place.
 struct SegArray64 {
   const double4* __restrict__ seg;
@@ -402,10 +385,11 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
 
 // FP64 path over FP64 segment quantities (m_x, m_y^2, d_y, c) of whole
 // loops or sub-loops, each formed from the FP32 points (exact but for one
-// rounding of m_y^2 and c), read from an array or formed in place (`fetch`,
-// SegArray64 or RawLoop): the midpoint's radius from m_x and m_y^2, and the
+// rounding of m_y^2 and c) and read from an array: the midpoint's radius
+// from m_x and m_y^2, and the
 // cross product's two parts summed apart as in the FP32 path,
-// cross = s^2 c + rho s d_y.  With EST, Q = sum_i qa_i^2.
+// cross = s^2 c + rho s d_y.  With EST, Q = sum_i qa_i^2.  `fetch` returns
+// segment i's quantities (SegArray64).
 template <int KIND, bool SPIN, bool EST, class Fetch>
 __device__ __forceinline__ void loop_sums_f64(const Fetch& fetch, int32_t n, double rho,
                                               double s, const FieldArgs& f, double& A,
@@ -429,6 +413,50 @@ __device__ __forceinline__ void loop_sums_f64(const Fetch& fetch, int32_t n, dou
   A = s2 * ac + (rho * s) * ad;
   B = kSpinSum ? b : (double)n;
   Q = q2;
+}
+
+// The FP64 sums of a (sub-)loop formed from its raw FP32 points: the
+// points first, first + stride, first + 2 stride, ... (indices mod N, m
+// segments), so {0, 1} is the whole loop and {0, 2}, {1, 4}, {3, 4} its
+// circle, square and triangle sub-loops.  Each segment's quantities are
+// those of the FP64 segment arrays (seg_quantities64) and the sums are
+// formed as loop_sums_f64 forms them, so the results equal the FP64 path's
+// bit for bit.  The points are wave-uniform: they arrive by scalar loads,
+// one point ahead, and only the segment in hand occupies vector registers.
+template <int KIND, bool SPIN>
+__device__ __forceinline__ void loop_sums_f64raw(const float* __restrict__ x,
+                                                 const float* __restrict__ y, int32_t n_ppl,
+                                                 int32_t first, int32_t stride, int32_t m,
+                                                 double rho, double s, const FieldArgs& f,
+                                                 double& A, double& B) {
+  constexpr bool kSpinSum = SPIN && KIND != kConst;
+  const double s2 = s * s;
+  double ac = 0.0, ad = 0.0, b = 0.0;
+  int32_t a = first;
+  float x0 = x[a], y0 = y[a];
+  int32_t nb = a + stride;
+  if (nb >= n_ppl) nb -= n_ppl;
+  float x1 = x[nb], y1 = y[nb];
+  for (int32_t j = 0; j < m; ++j) {
+    // the point after next is loaded while this segment is evaluated
+    int32_t nn = nb + stride;
+    if (nn >= n_ppl) nn -= n_ppl;
+    const float x2 = x[nn], y2 = y[nn];
+    const double4 q = seg_quantities64(x0, y0, x1, y1);
+    const double mx = fma(s, q.x, rho);
+    double qa, qb;
+    field_f64<KIND>(fma(mx, mx, fma(s2, q.y, 1e-300)), f, qa, qb);
+    ac = fma(q.w, qa, ac);
+    ad = fma(q.z, qa, ad);
+    if constexpr (kSpinSum) b += qb;
+    x0 = x1;
+    y0 = y1;
+    x1 = x2;
+    y1 = y2;
+    nb = nn;
+  }
+  A = s2 * ac + (rho * s) * ad;
+  B = kSpinSum ? b : (double)m;
 }
 
 template <int KIND, bool SPIN>
@@ -642,7 +670,11 @@ __device__ __forceinline__ void avg_loop(const float4* __restrict__ seg,
 
 // Item decomposition shared by the evaluation kernels: item = (group g,
 // loop sub-range, chunk of 64 grid points); loops [l0, l1); the partial
-// sums of the item land in row gs = g * n_sub + sub.
+// sums of the item land in row gs = g * n_sub + sub.  The evaluation kernels
+// number the items chunk-minor (consecutive items share their loops); the
+// FP64 recomputation numbers them chunk-major (chunk_major_item), so that
+// its few active items, the first chunks, are consecutive and spread over
+// every XCD and compute unit.
 struct ItemRange {
   int32_t chunk;
   int64_t gs, l0, l1;
@@ -660,6 +692,13 @@ __device__ __forceinline__ ItemRange item_range(int64_t item, int32_t n_chunks,
   const int64_t gend = (g + 1) * loops_per_group;
   if (r.l1 > gend) r.l1 = gend;
   return r;
+}
+
+// The chunk-minor item index of chunk-major index k over `rows` = G n_sub
+// rows and n_chunks chunks (a bijection of [0, rows n_chunks)).
+__device__ __forceinline__ int64_t chunk_major_item(int64_t k, int64_t rows,
+                                                    int32_t n_chunks) {
+  return (k % rows) * n_chunks + k / rows;
 }
 
 // One work item of a batch request.  Lane j owns grid point chunk*64 + j and
@@ -699,7 +738,7 @@ __device__ __forceinline__ void run_item(const float4* __restrict__ seg,
 // points in ascending order, count of them), so that every wave but the
 // last of a chunk row carries 64 flagged points; chunks past the count
 // return at once.  The sub-range's loops are walked in FP64 from the raw
-// points (RawLoop), their w summed as the FP64 path sums them, and each sum
+// points (loop_sums_f64raw), their w summed as the FP64 path sums them, and each sum
 // written over the item's FP32 partial sum of its point.
 template <int KIND, bool SPIN>
 __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
@@ -721,9 +760,9 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
   const double s = sqrt(T);
   double acc = 0.0;
   for (int64_t l = r.l0; l < r.l1; ++l) {
-    double A, B, Q, phi, S;
-    loop_sums_f64<KIND, SPIN, false>(RawLoop{X + l * n_ppl, Y + l * n_ppl, n_ppl, 0, 1},
-                                     n_ppl, rho, s, f, A, B, Q);
+    double A, B, phi, S;
+    loop_sums_f64raw<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, 0, 1, n_ppl, rho, s,
+                                 f, A, B);
     acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
   }
   if (esc) out[r.gs * n_pts + pg] = acc;
@@ -852,9 +891,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_escalate(
     int32_t n_pts, FieldArgs f, Sched sc, const int32_t* __restrict__ list,
     const int32_t* __restrict__ count, double* __restrict__ out) {
   const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t item = (int64_t)blockIdx.x * kWavesPerWG + wave;
-  if (item >= sc.n_items) return;
-  const ItemRange r = item_range(item, sc.n_chunks, sc.n_sub, sc.loops_per_group,
+  const int64_t k = (int64_t)blockIdx.x * kWavesPerWG + wave;
+  if (k >= sc.n_items) return;
+  const ItemRange r = item_range(chunk_major_item(k, sc.n_items / sc.n_chunks, sc.n_chunks),
+                                 sc.n_chunks, sc.n_sub, sc.loops_per_group,
                                  sc.loops_per_sub);
   escalate_item<KIND, SPIN>(X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f, r, list, count, out);
 }
@@ -1030,12 +1070,13 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_batch(
 
 // FP64 recomputation of the flagged grid points of a compensated-FP32
 // batch: the persistent item loop of k_batch over the same index space
-// (second counter), escalate_item per item.
+// (second counter, each request's items taken chunk-major), escalate_item
+// per item.
 __global__ __launch_bounds__(kWavesPerWG * kWave)
 __attribute__((amdgpu_waves_per_eu(4))) void k_escalate_batch(
     const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
     const BatchHeader* __restrict__ hdr, unsigned int* __restrict__ counter,
-    int64_t loops_per_group) {
+    int32_t n_groups, int64_t loops_per_group) {
   const ReqDesc* __restrict__ reqs =
       (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
   const int32_t n_reqs = (int32_t)hdr->n_reqs;
@@ -1052,8 +1093,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_escalate_batch(
       if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
     }
     const ReqDesc& q = reqs[lo];
-    const ItemRange r = item_range(item - q.item_begin, q.n_chunks, q.n_sub,
-                                   loops_per_group, q.loops_per_sub);
+    const ItemRange r = item_range(
+        chunk_major_item(item - q.item_begin, (int64_t)n_groups * q.n_sub, q.n_chunks),
+        q.n_chunks, q.n_sub, loops_per_group, q.loops_per_sub);
     switch (q.f.kind * 2 + q.spin) {
 #define WL_ESC(K, SP) \
   escalate_item<K, SP>(X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f, r, q.list, q.count, q.out)
@@ -1226,10 +1268,9 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
     const double l2 = fabs(f.cphi32) * sqrt(Q);
     const bool esc = valid && kPhaseK * kU32 * l2 > 1e-5 * fmax(1.0, fabs(phi));
     if (__ballot(esc) != 0) {
-      double A64, B64, Q64, phi64, S64;
-      loop_sums_f64<KIND, SPIN, false>(
-          RawLoop{X + l * n_ppl, Y + l * n_ppl, n_ppl, sl.first, sl.stride}, sl.m, rho, s,
-          f, A64, B64, Q64);
+      double A64, B64, phi64, S64;
+      loop_sums_f64raw<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, sl.first, sl.stride,
+                                   sl.m, rho, s, f, A64, B64);
       const double w64 = epilogue<SPIN, 2>(A64, B64, T, sl.m, f, phi64, S64);
       if (esc) {
         phi = phi64;
@@ -1677,7 +1718,7 @@ hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg
     hipLaunchKernelGGL(k_compact_batch, dim3(256), dim3(kCompactThreads), 0, stream, hdr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_escalate_batch, dim3(n_wg), blk, 0, stream, d_x, d_y, n_ppl, hdr,
-                       d_counter + 1, lpg);
+                       d_counter + 1, n_groups, lpg);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_reduce_batch, dim3(2048), dim3(256), 0, stream, hdr, d_res);

@@ -220,8 +220,10 @@ int wl_average_ex(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
 
 /* As wl_average, but every array is DEVICE memory on the ctx device and
  * the call only enqueues work on the ctx stream (no host synchronisation).
- * d_rho, d_T must stay valid and unchanged until the work completes, and
- * their values are NOT validated (the caller guarantees rho >= 0, T > 0).
+ * d_rho, d_T must stay valid and unchanged until the work completes.
+ * Their values are not checked on the host: a grid point with rho < 0,
+ * T <= 0 or a non-finite value gets NaN in every output at that point (the
+ * others are unaffected).
  * d_group_sums is required; d_mean and d_err may be NULL.  The library may
  * use its own device scratch buffer, so calls on one ctx are serialised on
  * its stream. */

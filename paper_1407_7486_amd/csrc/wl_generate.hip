@@ -53,56 +53,85 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
   out[3] = c3;
 }
 
-// One workgroup per loop (grid-stride over loops), one coordinate per pass
-// (comp 0: x from the cosines, 1: y from the sines): the loop's N FP64
-// values sit in LDS (8N bytes).  Threads take the new points of a level;
-// a barrier separates the levels.
+// One workgroup per loop (grid-stride over loops), both coordinates in one
+// pass: the loop's N FP64 x and y values sit in LDS (16N bytes).  At each
+// level the threads take the Philox blocks of the level's new points: a
+// block feeds the (one or two) new points of that level whose ordinals it
+// covers, so that each block, logarithm and square root is computed once
+// (only a block straddling two levels is computed once per level).  A
+// barrier separates the levels.
 __global__ __launch_bounds__(256) void k_generate(uint64_t seed, int64_t first_loop,
                                                   int64_t n_loops, int32_t n_ppl,
-                                                  int32_t comp, float* __restrict__ out) {
+                                                  float* __restrict__ out_x,
+                                                  float* __restrict__ out_y) {
 #pragma clang fp contract(off)
   extern __shared__ double v[];
-  __shared__ double part[256];
+  double* vx = v;
+  double* vy = v + n_ppl;
+  __shared__ double part[2][256];
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const double two_pi = 6.283185307179586476925286766559;
   const double inv32 = 1.0 / 4294967296.0;
   for (int64_t l = blockIdx.x; l < n_loops; l += gridDim.x) {
     const uint64_t gl = (uint64_t)(first_loop + l);
-    if (threadIdx.x == 0) v[0] = 0.0;
+    if (threadIdx.x == 0) {
+      vx[0] = 0.0;
+      vy[0] = 0.0;
+    }
     __syncthreads();
     for (int32_t nk = 2; nk <= n_ppl; nk *= 2) {
       const int32_t h = n_ppl / nk;
       const double sigma = 1.0 / sqrt((double)nk);
-      for (int32_t qi = threadIdx.x; qi < nk / 2; qi += blockDim.x) {
-        const int32_t i = (2 * qi + 1) * h;
-        const int32_t a = i - h;
-        const int32_t b = (i + h == n_ppl) ? 0 : i + h;
-        const int64_t p = (int64_t)(nk / 2 - 1) + qi;  // ordinal of the new point
+      // ordinals of this level's new points: o0 .. o1
+      const int64_t o0 = nk / 2 - 1, o1 = nk - 2;
+      for (int64_t bb = (o0 >> 1) + threadIdx.x; bb <= (o1 >> 1); bb += blockDim.x) {
         uint32_t w[4];
-        philox4x32_10((uint32_t)(p >> 1), (uint32_t)gl, (uint32_t)(gl >> 32), 0u, k0, k1, w);
-        const int pr = (int)(p & 1);
-        const double u1 = ((double)w[2 * pr] + 0.5) * inv32;
-        const double u2 = ((double)w[2 * pr + 1] + 0.5) * inv32;
-        const double r = sqrt(-2.0 * log(u1));
-        const double z = comp == 0 ? r * cos(two_pi * u2) : r * sin(two_pi * u2);
-        const double mid = 0.5 * (v[a] + v[b]);
-        const double dz = sigma * z;
-        v[i] = mid + dz;
+        philox4x32_10((uint32_t)bb, (uint32_t)gl, (uint32_t)(gl >> 32), 0u, k0, k1, w);
+        for (int pr = 0; pr < 2; ++pr) {
+          const int64_t p = 2 * bb + pr;  // ordinal of the new point
+          if (p < o0 || p > o1) continue;
+          const int32_t qi = (int32_t)(p - o0);
+          const int32_t i = (2 * qi + 1) * h;
+          const int32_t a = i - h;
+          const int32_t b = (i + h == n_ppl) ? 0 : i + h;
+          const double u1 = ((double)w[2 * pr] + 0.5) * inv32;
+          const double u2 = ((double)w[2 * pr + 1] + 0.5) * inv32;
+          const double r = sqrt(-2.0 * log(u1));
+          const double zx = r * cos(two_pi * u2);
+          const double zy = r * sin(two_pi * u2);
+          const double mx = 0.5 * (vx[a] + vx[b]);
+          const double my = 0.5 * (vy[a] + vy[b]);
+          const double dx = sigma * zx;
+          const double dy = sigma * zy;
+          vx[i] = mx + dx;
+          vy[i] = my + dy;
+        }
       }
       __syncthreads();
     }
     // centre of mass
-    double s = 0.0;
-    for (int32_t i = threadIdx.x; i < n_ppl; i += blockDim.x) s += v[i];
-    part[threadIdx.x] = s;
+    double sx = 0.0, sy = 0.0;
+    for (int32_t i = threadIdx.x; i < n_ppl; i += blockDim.x) {
+      sx += vx[i];
+      sy += vy[i];
+    }
+    part[0][threadIdx.x] = sx;
+    part[1][threadIdx.x] = sy;
     __syncthreads();
     for (int32_t w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int32_t)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+      if ((int32_t)threadIdx.x < w) {
+        part[0][threadIdx.x] += part[0][threadIdx.x + w];
+        part[1][threadIdx.x] += part[1][threadIdx.x + w];
+      }
       __syncthreads();
     }
-    const double mean = part[0] / n_ppl;
-    float* o = out + l * n_ppl;
-    for (int32_t i = threadIdx.x; i < n_ppl; i += blockDim.x) o[i] = (float)(v[i] - mean);
+    const double mean_x = part[0][0] / n_ppl, mean_y = part[1][0] / n_ppl;
+    float* ox = out_x + l * n_ppl;
+    float* oy = out_y + l * n_ppl;
+    for (int32_t i = threadIdx.x; i < n_ppl; i += blockDim.x) {
+      ox[i] = (float)(vx[i] - mean_x);
+      oy[i] = (float)(vy[i] - mean_y);
+    }
     __syncthreads();  // v and part are reused by the next loop
   }
 }
@@ -111,15 +140,14 @@ __global__ __launch_bounds__(256) void k_generate(uint64_t seed, int64_t first_l
 
 hipError_t launch_generate(uint64_t seed, int64_t first_loop, int64_t n_loops, int32_t n_ppl,
                            float* d_x, float* d_y, hipStream_t stream) {
-  int64_t blocks = n_loops < 65536 ? n_loops : 65536;
-  const size_t lds = (size_t)n_ppl * sizeof(double);
-  for (int comp = 0; comp < 2; ++comp) {
-    hipLaunchKernelGGL(k_generate, dim3((uint32_t)blocks), dim3(256), lds, stream, seed,
-                       first_loop, n_loops, n_ppl, comp, comp == 0 ? d_x : d_y);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const int64_t blocks = n_loops < 65536 ? n_loops : 65536;
+  const size_t lds = 2 * (size_t)n_ppl * sizeof(double);  // at most 128 KiB (N <= 8192)
+  hipError_t e = hipFuncSetAttribute((const void*)k_generate,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_generate, dim3((uint32_t)blocks), dim3(256), lds, stream, seed,
+                     first_loop, n_loops, n_ppl, d_x, d_y);
+  return hipGetLastError();
 }
 
 }  // namespace wl

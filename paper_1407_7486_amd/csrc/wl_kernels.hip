@@ -668,6 +668,11 @@ __device__ __forceinline__ void avg_loop(const float4* __restrict__ seg,
              v);
 }
 
+// The domain of a grid point: rho_cm >= 0 and T > 0, both finite.
+__device__ __forceinline__ bool grid_ok(double rho, double T) {
+  return rho >= 0.0 && T > 0.0 && rho < INFINITY && T < INFINITY;
+}
+
 // Item decomposition shared by the evaluation kernels: item = (group g,
 // loop sub-range, chunk of 64 grid points); loops [l0, l1); the partial
 // sums of the item land in row gs = g * n_sub + sub.  The evaluation kernels
@@ -874,9 +879,12 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
   }
   if (valid) {
     const int64_t o = r.gs * n_pts + pg;
-    out[o] = acc;
-    out_a[o] = a;
-    out_v[o] = v;
+    // a grid point outside the domain (device grids are not validated on
+    // the host) gives NaN, whatever its arithmetic produced
+    const double bad = grid_ok(rho, T) ? 0.0 : NAN;
+    out[o] = acc + bad;
+    out_a[o] = a + bad;
+    out_v[o] = v + bad;
   }
 }
 

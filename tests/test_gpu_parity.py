@@ -403,3 +403,42 @@ def test_maximum_size_sampled(wl, ctx):
     finally:
         wl.wl_ensemble_free(ens)
         del x, y
+
+
+def test_async_device_grid_outside_domain(wl):
+    """Device grids are not checked on the host: a point with rho < 0 or
+    T <= 0 gets NaN in every output at that point, the other points equal
+    the synchronous evaluation of the valid grid bit for bit."""
+    import torch
+    say("async grid outside the domain")
+    dev = torch.device("cuda:0")
+    ctx = wl.wl_create(0, torch.cuda.current_stream(dev).cuda_stream)
+    x, y = wlinputs.polygon_loops(64, 203, seed=31)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 4)
+    try:
+        fld = wl.field(1, 1.3, 0.7)
+        rho = np.array([0.0, -1.0, 1.1, 2.5])
+        T = np.array([1e-3, 0.0, 0.5, 3.0, 20.0])
+        G, n = 4, rho.size * T.size
+        d = {k: torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+             for k in ("mean", "err", "scale", "fp_err")}
+        d["group_sums"] = torch.full((G * n,), float("nan"), dtype=torch.float64, device=dev)
+        wl.wl_average_ex_device(ctx, ens, fld, torch.tensor(rho, device=dev),
+                                torch.tensor(T, device=dev), 1, wl.WL_FP32C, d)
+        torch.cuda.synchronize(dev)
+        got = {k: v.cpu().numpy().reshape((G, rho.size, T.size) if k == "group_sums"
+                                          else (rho.size, T.size)) for k, v in d.items()}
+        bad = np.zeros((rho.size, T.size), dtype=bool)
+        bad[1, :] = True
+        bad[:, 1] = True
+        for k, v in got.items():
+            vv = v if k != "group_sums" else v.transpose(1, 2, 0)
+            assert np.isnan(vv[bad]).all(), k
+        ok_r, ok_t = np.array([0, 2, 3]), np.array([0, 2, 3, 4])
+        ref = wl.wl_average_ex(ctx, ens, fld, rho[ok_r], T[ok_t], 1, wl.WL_FP32C)
+        for k in ("mean", "err", "scale", "fp_err", "group_sums"):
+            sub = got[k][..., ok_r, :][..., ok_t]
+            assert np.array_equal(sub, ref[k]), k
+    finally:
+        wl.wl_ensemble_free(ens)
+        wl.wl_destroy(ctx)

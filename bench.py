@@ -299,6 +299,9 @@ def main():
                     help="arrival rate of the serving point below capacity, requests/s")
     ap.add_argument("--serve-requests-low", type=int, default=16,
                     help="requests of the serving point below capacity")
+    ap.add_argument("--c4-requests", type=int, default=256,
+                    help="uneven requests (seed 1) batched in one persistent launch on the "
+                         "resident ensemble (0: skip)")
     ap.add_argument("--no-c3", dest="c3", action="store_false",
                     help="skip the precision-stress evaluation (131072 x 8192 loops, "
                          "32 x 48 grid, sech^2 B0 = 20, lambda = 4, spinor)")
@@ -525,6 +528,27 @@ def main():
     if args.c3:
         c3 = c3_run(wl, ctx, torch, dev, precision_report)
 
+    c4 = None
+    if args.c4_requests > 0:
+        # uneven requests against the resident ensemble in one persistent launch
+        reqs = wlinputs.draw_requests(args.c4_requests, seed=1)
+        for q in reqs:
+            q["precision"] = wl.WL_FP32C
+        segs = sum(q["rho"].size * q["T"].size for q in reqs) * cfg["n_loops"] * cfg["n_ppl"]
+        pts = sum(q["rho"].size * q["T"].size for q in reqs)
+        log(f"[bench] c4: {len(reqs)} requests, {segs:.3e} segment evaluations")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs4 = wl.wl_average_batch(ctx, ens, reqs, full=True)
+        dt4 = time.perf_counter() - t0
+        esc = sum(int(o["escalated"].sum()) for o in outs4)
+        c4 = {"requests": len(reqs), "segment_evals": segs, "wall_s": dt4,
+              "segment_evals_per_s": segs / dt4, "launches": 1,
+              "escalated_fraction": esc / pts,
+              "finite": all(bool(np.isfinite(o["mean"]).all()) for o in outs4)}
+        log(f"[bench] c4 {segs / dt4:.4e} seg/s in {dt4:.1f} s, {esc} of {pts} points "
+            f"recomputed in FP64")
+
     cpu = None
     if args.cpu_loops > 0:
         import oracle
@@ -579,7 +603,8 @@ def main():
                    "n_ppl": cfg["n_ppl"], "n_rho": int(rho.size), "n_T": int(T.size),
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
-        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "c3": c3, "serve": serve,
+        "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "c3": c3, "c4": c4,
+        "serve": serve,
         "serve_sub_capacity": serve_low, "disc": disc, "generate": gen, "correlation": corr,
     }
     print(json.dumps(out), flush=True)

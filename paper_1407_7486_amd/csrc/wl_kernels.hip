@@ -775,8 +775,10 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
 
 // The flagged grid points of one evaluation in ascending order, list[0 ..
 // count), by one workgroup of kCompactThreads: per tile of that many points
-// a wave ballot and popcount give each flagged point its rank.
-constexpr int kCompactThreads = 1024;
+// a wave ballot and popcount give each flagged point its rank.  Four waves:
+// a workgroup this small finds room on a compute unit beside another
+// server slot's persistent batch kernel as soon as one wave per SIMD drains.
+constexpr int kCompactThreads = 256;
 __device__ __forceinline__ void compact_flags(const uint8_t* __restrict__ flags,
                                               int32_t n_pts, int32_t* __restrict__ list,
                                               int32_t* __restrict__ count) {

@@ -160,12 +160,14 @@ ReqPlan plan_request(const wl_ctx* ctx, const wl_ens* ens, const wl_request& q) 
   p.in_bytes = sizeof(ReqDesc) + 8 * (size_t)(q.n_rho + q.n_T);
   // group sums, mean, err, scale, fp_err, escalation flags (one byte per
   // point, padded to 8 with the other requests'), the item scale and
-  // rounding accumulators, and the item partial sums of w when split
+  // rounding accumulators, the item partial sums of w when split, the
+  // compacted list of flagged points with its count, and the request's
+  // row of the FP64 recomputation table, 8 x 8 bytes (with room for the
+  // table's final row and the alignments, also for a batch of one)
   const size_t part = (size_t)G * p.s.n_sub * p.n_pts;
-  // (+ the compacted list of flagged points and its count)
   p.res_bytes = 8 * ((size_t)G * p.n_pts + 4 * (size_t)p.n_pts + 2 * part +
                      (p.s.n_sub > 1 ? part : 0)) +
-                (size_t)p.n_pts + 8 + 4 * (size_t)p.n_pts + 8;
+                (size_t)p.n_pts + 8 + 4 * (size_t)p.n_pts + 8 + 2 * 8 * 8 + 32;
   return p;
 }
 
@@ -188,7 +190,7 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
   lay->head_bytes = 8 * (size_t)(lay->sums_n + 4 * lay->pts_n) +
                     (((size_t)lay->pts_n + 7) & ~(size_t)7);
   lay->res_bytes = lay->head_bytes + 8 * (size_t)(2 * lay->acc_n + lay->part_n) +
-                   4 * (size_t)(lay->pts_n + n) + 8;
+                   4 * (size_t)(lay->pts_n + n) + 8 + 8 * 8 * ((size_t)n + 1);
   if (lay->in_bytes > cap_in || lay->res_bytes > cap_res) return false;
   char* hb = (char*)h_in;
   BatchHeader* hdr = (BatchHeader*)hb;
@@ -209,6 +211,8 @@ bool build_batch(const wl_ens* ens, const wl_request* const* reqs, const FieldAr
   double* d_part = d_acc_v + lay->acc_n;
   int32_t* d_list = (int32_t*)(d_part + lay->part_n);  // [pts_n] lists, then [n] counts
   int32_t* d_count = d_list + lay->pts_n;
+  int64_t* d_esc_begin = (int64_t*)(((uintptr_t)(d_count + n) + 7) & ~(uintptr_t)7);
+  hdr->esc_begin = d_esc_begin;
   int64_t items = 0, sums = 0, pts = 0, part = 0, acc = 0, go = 0;
   for (int32_t i = 0; i < n; ++i) {
     const wl_request& q = *reqs[i];
@@ -382,7 +386,7 @@ int wl_create(wl_ctx** out, int device, void* hip_stream) {
   c->num_cu = prop.multiProcessorCount;
   DeviceGuard g(device);
   if (g.status != hipSuccess || hipMalloc((void**)&c->d_flag, sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&c->d_counter, 2 * sizeof(unsigned int)) != hipSuccess) {
+      hipMalloc((void**)&c->d_counter, kBatchCounters * sizeof(unsigned int)) != hipSuccess) {
     wl_destroy(c);
     return WL_ENOMEM;
   }

@@ -27,7 +27,7 @@ struct wl_ctx {
   int* d_flag = nullptr;
   void* d_batch = nullptr;  // batched evaluation: descriptors, grids, results
   size_t batch_bytes = 0;
-  unsigned int* d_counter = nullptr;  // two work counters of persistent launches
+  unsigned int* d_counter = nullptr;  // work counters of persistent launches
   // device address of the allocation-free entry point's static scratch
   // array on this context's device (nullptr if it could not be obtained;
   // noalloc_status then holds the HIP error)

@@ -65,7 +65,12 @@ struct BatchHeader {
   int64_t total_items;
   int64_t total_sums;
   int64_t total_pts;
+  int64_t* esc_begin;  // [8][n_reqs + 1] first FP64 recomputation item per
+                       // request, per field kind x spin
 };
+// Work counters of a batch: the item loop, and one per field kind x spin
+// for the FP64 recomputation.
+constexpr int kBatchCounters = 9;
 constexpr size_t kBatchDescOffset = 64;
 
 // One request of a batched evaluation (device-resident descriptor).
@@ -183,8 +188,9 @@ hipError_t launch_disc_finish(double* d_sums, int32_t n_groups, int32_t n_pts,
 // (BatchHeader followed by the descriptors, whose pointers place every
 // array).  Results at d_res: [group sums | means | errors | scales |
 // rounding estimates | flags | ...] with the sizes from the header.  Grid
-// sizes are fixed (n_wg persistent workgroups) and d_counter holds two
-// work counters, so the sequence can be captured once and replayed.
+// sizes are fixed (n_wg persistent workgroups) and d_counter holds
+// kBatchCounters work counters, so the sequence can be captured once and
+// replayed.
 hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg64,
                         const float2* d_norm, const float* d_x, const float* d_y,
                         int32_t n_ppl, const void* d_hdr, int32_t n_groups, int64_t n_loops,

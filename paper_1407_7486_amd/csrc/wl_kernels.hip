@@ -675,11 +675,8 @@ __device__ __forceinline__ bool grid_ok(double rho, double T) {
 
 // Item decomposition shared by the evaluation kernels: item = (group g,
 // loop sub-range, chunk of 64 grid points); loops [l0, l1); the partial
-// sums of the item land in row gs = g * n_sub + sub.  The evaluation kernels
-// number the items chunk-minor (consecutive items share their loops); the
-// FP64 recomputation numbers them chunk-major (chunk_major_item), so that
-// its few active items, the first chunks, are consecutive and spread over
-// every XCD and compute unit.
+// sums of the item land in row gs = g * n_sub + sub.  Items are numbered
+// chunk-minor: consecutive items share their loops.
 struct ItemRange {
   int32_t chunk;
   int64_t gs, l0, l1;
@@ -697,13 +694,6 @@ __device__ __forceinline__ ItemRange item_range(int64_t item, int32_t n_chunks,
   const int64_t gend = (g + 1) * loops_per_group;
   if (r.l1 > gend) r.l1 = gend;
   return r;
-}
-
-// The chunk-minor item index of chunk-major index k over `rows` = G n_sub
-// rows and n_chunks chunks (a bijection of [0, rows n_chunks)).
-__device__ __forceinline__ int64_t chunk_major_item(int64_t k, int64_t rows,
-                                                    int32_t n_chunks) {
-  return (k % rows) * n_chunks + k / rows;
 }
 
 // One work item of a batch request.  Lane j owns grid point chunk*64 + j and
@@ -738,39 +728,51 @@ __device__ __forceinline__ void run_item(const float4* __restrict__ seg,
   }
 }
 
-// The FP64 recomputation of one work item of the flagged grid points: chunk
-// c of the item takes the points list[64 c .. 64 c + 63] (the flagged
-// points in ascending order, count of them), so that every wave but the
-// last of a chunk row carries 64 flagged points; chunks past the count
-// return at once.  The sub-range's loops are walked in FP64 from the raw
-// points (loop_sums_f64raw), their w summed as the FP64 path sums them, and each sum
-// written over the item's FP32 partial sum of its point.
+// The FP64 recomputation of the flagged grid points, in work items (row gs
+// = g n_sub + sub of the evaluation's partial sums, chunk c of the flagged
+// points): the sub-range's loops are walked in FP64 from the raw points
+// (loop_sums_f64raw, the FP64 path's arithmetic, each loop's points coming
+// in through scalar loads that the whole wave shares) for the flagged
+// points list[64 c .. 64 c + 63] (ascending, cnt of them), one per lane,
+// and each point's sum of w over the sub-range is written over the item's
+// FP32 partial sum.  Items are numbered chunk-major, k = c rows + gs
+// (rows = G n_sub), so that the items of a small count, one chunk, lie
+// side by side and spread over every XCD and compute unit.
+constexpr int kEscWaves = 3;  // waves per SIMD of the recomputation kernels
+__device__ __forceinline__ int64_t esc_items(int64_t rows, int32_t cnt) {
+  return rows * (((int64_t)cnt + kWave - 1) / kWave);
+}
+
 template <int KIND, bool SPIN>
 __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
                                               const float* __restrict__ Y, int32_t n_ppl,
                                               const double* __restrict__ rho_g,
                                               const double* __restrict__ T_g, int32_t n_T,
-                                              int32_t n_pts, const FieldArgs& f,
-                                              const ItemRange& r,
-                                              const int32_t* __restrict__ list,
-                                              const int32_t* __restrict__ count,
+                                              int32_t n_pts, const FieldArgs& f, int64_t k,
+                                              int64_t rows, int32_t n_sub,
+                                              int64_t loops_per_group, int64_t loops_per_sub,
+                                              const int32_t* __restrict__ list, int32_t cnt,
                                               double* __restrict__ out) {
-  const int32_t cnt = __builtin_amdgcn_readfirstlane(*count);
-  if ((int64_t)r.chunk * kWave >= cnt) return;
-  const int32_t j = r.chunk * kWave + (int32_t)(threadIdx.x % kWave);
+  const int32_t chunk = (int32_t)(k / rows);
+  const int64_t gs = k % rows;
+  const int64_t g = gs / n_sub;
+  const int64_t l0 = g * loops_per_group + (gs % n_sub) * loops_per_sub;
+  int64_t l1 = l0 + loops_per_sub;
+  if (l1 > (g + 1) * loops_per_group) l1 = (g + 1) * loops_per_group;
+  const int32_t j = chunk * kWave + (int32_t)(threadIdx.x % kWave);
   const bool esc = j < cnt;
   const int32_t pg = list[esc ? j : cnt - 1];
   const double rho = rho_g[pg / n_T];
   const double T = T_g[pg % n_T];
   const double s = sqrt(T);
   double acc = 0.0;
-  for (int64_t l = r.l0; l < r.l1; ++l) {
+  for (int64_t l = l0; l < l1; ++l) {
     double A, B, phi, S;
     loop_sums_f64raw<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, 0, 1, n_ppl, rho, s,
                                  f, A, B);
     acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
   }
-  if (esc) out[r.gs * n_pts + pg] = acc;
+  if (esc) out[gs * n_pts + pg] = acc;
 }
 
 // The flagged grid points of one evaluation in ascending order, list[0 ..
@@ -890,23 +892,26 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
   }
 }
 
-// FP64 recomputation of the flagged grid points of an evaluation
-// (escalate_item per work item; four waves per workgroup, no barrier).
-// FP64-path register budget: 128 VGPRs, 4 waves per SIMD.
+// FP64 recomputation of the flagged grid points of an evaluation: the
+// G n_sub ceil(count / 64) items of escalate_item, grid-stride (four waves
+// per workgroup, no barrier).  Register budget 168 VGPRs, 3 waves per SIMD:
+// at 128 (4 waves) the sech^2 and Gaussian walks spill inside the segment
+// loop (the sech^2 spinor one 15 scratch accesses per segment).
 template <int KIND, bool SPIN>
 __global__ __launch_bounds__(kWavesPerWG * kWave)
-__attribute__((amdgpu_waves_per_eu(4))) void k_escalate(
+__attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate(
     const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g, int32_t n_T,
     int32_t n_pts, FieldArgs f, Sched sc, const int32_t* __restrict__ list,
     const int32_t* __restrict__ count, double* __restrict__ out) {
   const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t k = (int64_t)blockIdx.x * kWavesPerWG + wave;
-  if (k >= sc.n_items) return;
-  const ItemRange r = item_range(chunk_major_item(k, sc.n_items / sc.n_chunks, sc.n_chunks),
-                                 sc.n_chunks, sc.n_sub, sc.loops_per_group,
-                                 sc.loops_per_sub);
-  escalate_item<KIND, SPIN>(X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f, r, list, count, out);
+  const int32_t cnt = __builtin_amdgcn_readfirstlane(*count);
+  const int64_t rows = sc.n_items / sc.n_chunks;
+  const int64_t total = esc_items(rows, cnt);
+  for (int64_t k = (int64_t)blockIdx.x * kWavesPerWG + wave; k < total;
+       k += (int64_t)gridDim.x * kWavesPerWG)
+    escalate_item<KIND, SPIN>(X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f, k, rows, sc.n_sub,
+                              sc.loops_per_group, sc.loops_per_sub, list, cnt, out);
 }
 
 // The flagged points of one evaluation, compacted (compact_flags).
@@ -1025,6 +1030,26 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 6))) void k_disc(
   }
 }
 
+// Next item of a persistent wavefront's work loop: one increment of the
+// counter per wave, whose old value every lane receives.  Every lane
+// executes the atomic (lane 0 adds 1, the others 0; the compiler folds the
+// wave's lanes into one memory operation), so that no lane-dependent branch
+// sits in the loop: around a branch on the lane the compiler may send lanes
+// 1..63 from the end of one item straight back to the broadcast, where they
+// then run without lane 0 and read a stale item.
+__device__ __forceinline__ int64_t take_item(unsigned int* counter) {
+  const unsigned int t = atomicAdd(counter, threadIdx.x % kWave == 0 ? 1u : 0u);
+  return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+}
+
+// A value every lane of the wave holds, moved to scalar registers, so that
+// branches on it are taken by the whole wave.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Batched evaluation of uneven requests in one persistent launch.  Items of
 // all requests form one index space (request r owns [item_begin_r,
 // item_begin_r + n_items_r)); each wavefront repeatedly takes the next item
@@ -1049,11 +1074,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_batch(
       (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
   const int32_t n_reqs = (int32_t)hdr->n_reqs;
   const int64_t total_items = hdr->total_items;
-  const int32_t lane = threadIdx.x % kWave;
   for (;;) {
-    unsigned int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1u);
-    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)t) & 0xffffffffll;
+    const int64_t item = take_item(counter);
     if (item >= total_items) break;
     // request owning the item: last r with item_begin <= item
     int32_t lo = 0, hi = n_reqs - 1;
@@ -1079,46 +1101,64 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_batch(
 }
 
 // FP64 recomputation of the flagged grid points of a compensated-FP32
-// batch: the persistent item loop of k_batch over the same index space
-// (second counter, each request's items taken chunk-major), escalate_item
-// per item.
+// batch, one kernel per field kind and spin (a kernel holding every
+// variant would spill inside the segment walks): a persistent loop over the
+// escalate_item items of the batch's requests of that variant, taken from
+// the variant's work counter; the header's esc_begin table of the variant,
+// [n_reqs + 1], holds the first item of each request (k_esc_begin; requests
+// of other variants have none).
+constexpr int kVariants = 8;  // field kind x spin
+template <int KIND, bool SPIN>
 __global__ __launch_bounds__(kWavesPerWG * kWave)
-__attribute__((amdgpu_waves_per_eu(4))) void k_escalate_batch(
+__attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate_batch(
     const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
     const BatchHeader* __restrict__ hdr, unsigned int* __restrict__ counter,
     int32_t n_groups, int64_t loops_per_group) {
   const ReqDesc* __restrict__ reqs =
       (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
   const int32_t n_reqs = (int32_t)hdr->n_reqs;
-  const int64_t total_items = hdr->total_items;
-  const int32_t lane = threadIdx.x % kWave;
+  const int64_t* __restrict__ esc_begin =
+      hdr->esc_begin + (int64_t)(KIND * 2 + (SPIN ? 1 : 0)) * (n_reqs + 1);
+  // the table is written by an earlier kernel, so its entries come in
+  // through vector loads: wave_uniform keeps the loop's branches scalar
+  const int64_t total = wave_uniform(esc_begin[n_reqs]);
   for (;;) {
-    unsigned int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1u);
-    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)t) & 0xffffffffll;
-    if (item >= total_items) break;
+    const int64_t item = take_item(counter);
+    if (item >= total) break;
+    // request owning the item: last r with esc_begin[r] <= item (a request
+    // without items has the same entry as the next one and is passed over)
     int32_t lo = 0, hi = n_reqs - 1;
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) >> 1;
-      if (reqs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+      if (wave_uniform(esc_begin[mid]) <= item) lo = mid; else hi = mid - 1;
     }
     const ReqDesc& q = reqs[lo];
-    const ItemRange r = item_range(
-        chunk_major_item(item - q.item_begin, (int64_t)n_groups * q.n_sub, q.n_chunks),
-        q.n_chunks, q.n_sub, loops_per_group, q.loops_per_sub);
-    switch (q.f.kind * 2 + q.spin) {
-#define WL_ESC(K, SP) \
-  escalate_item<K, SP>(X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f, r, q.list, q.count, q.out)
-      case 0: WL_ESC(kConst, false); break;
-      case 1: WL_ESC(kConst, true); break;
-      case 2: WL_ESC(kSech2, false); break;
-      case 3: WL_ESC(kSech2, true); break;
-      case 4: WL_ESC(kGauss, false); break;
-      case 5: WL_ESC(kGauss, true); break;
-      case 6: WL_ESC(kRational, false); break;
-      default: WL_ESC(kRational, true); break;
-#undef WL_ESC
-    }
+    const int32_t cnt = __builtin_amdgcn_readfirstlane(*q.count);
+    escalate_item<KIND, SPIN>(X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f,
+                              item - wave_uniform(esc_begin[lo]), (int64_t)n_groups * q.n_sub,
+                              q.n_sub, loops_per_group, q.loops_per_sub, q.list, cnt, q.out);
+  }
+}
+
+// First recomputation item of each request of a batch, per variant (one
+// thread, in request order): for the request's variant v,
+// esc_begin[v][r + 1] = esc_begin[v][r] + G n_sub_r ceil(count_r / 64);
+// the other variants' tables repeat their entry.
+__global__ void k_esc_begin(const BatchHeader* __restrict__ hdr, int32_t n_groups,
+                            int64_t loops_per_group) {
+  const ReqDesc* __restrict__ reqs =
+      (const ReqDesc*)((const char*)hdr + kBatchDescOffset);
+  const int32_t n_reqs = (int32_t)hdr->n_reqs;
+  int64_t* __restrict__ esc_begin = hdr->esc_begin;
+  int64_t acc[kVariants];
+  for (int v = 0; v < kVariants; ++v) {
+    acc[v] = 0;
+    esc_begin[(int64_t)v * (n_reqs + 1)] = 0;
+  }
+  for (int32_t r = 0; r < n_reqs; ++r) {
+    const int v = reqs[r].f.kind * 2 + (reqs[r].spin ? 1 : 0);
+    acc[v] += esc_items((int64_t)n_groups * reqs[r].n_sub, *reqs[r].count);
+    for (int u = 0; u < kVariants; ++u) esc_begin[(int64_t)u * (n_reqs + 1) + r + 1] = acc[u];
   }
 }
 
@@ -1505,7 +1545,11 @@ hipError_t launch_esc_t(const FieldArgs& f, const float* x, const float* y, int3
                      count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t n_wg = (s.n_items + kWavesPerWG - 1) / kWavesPerWG;
+  // at most n_pts points flagged: enough workgroups for the largest count
+  // (the evaluation's n_items items), up to 4096 (16384 waves, 4 per SIMD on
+  // 1024 SIMDs four times over)
+  int64_t n_wg = (s.n_items + kWavesPerWG - 1) / kWavesPerWG;
+  if (n_wg > 4096) n_wg = 4096;
   hipLaunchKernelGGL((k_escalate<KIND, SPIN>), dim3((uint32_t)n_wg), dim3(kWavesPerWG * kWave),
                      0, st, x, y, n_ppl, rho, T, n_T, n_pts, f, s, list, count, out);
   return hipGetLastError();
@@ -1700,7 +1744,7 @@ hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg
   if (precision == 2 ? d_seg64 == nullptr : d_seg == nullptr) return hipErrorInvalidValue;
   const BatchHeader* hdr = (const BatchHeader*)d_hdr;
   const int64_t lpg = n_loops / n_groups;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(2), 0, stream, d_counter);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBatchCounters), 0, stream, d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 blk(kWavesPerWG * kWave);
@@ -1727,9 +1771,21 @@ hipError_t launch_batch(int precision, const float4* d_seg, const double4* d_seg
   if (precision == 0) {
     hipLaunchKernelGGL(k_compact_batch, dim3(256), dim3(kCompactThreads), 0, stream, hdr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_escalate_batch, dim3(n_wg), blk, 0, stream, d_x, d_y, n_ppl, hdr,
-                       d_counter + 1, n_groups, lpg);
+    hipLaunchKernelGGL(k_esc_begin, dim3(1), dim3(1), 0, stream, hdr, n_groups, lpg);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+#define WL_ESCB(K, SP, V)                                                              \
+  hipLaunchKernelGGL((k_escalate_batch<K, SP>), dim3(n_wg), blk, 0, stream, d_x, d_y, n_ppl, \
+                     hdr, d_counter + 1 + (V), n_groups, lpg);                          \
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+    WL_ESCB(kConst, false, 0)
+    WL_ESCB(kConst, true, 1)
+    WL_ESCB(kSech2, false, 2)
+    WL_ESCB(kSech2, true, 3)
+    WL_ESCB(kGauss, false, 4)
+    WL_ESCB(kGauss, true, 5)
+    WL_ESCB(kRational, false, 6)
+    WL_ESCB(kRational, true, 7)
+#undef WL_ESCB
   }
   hipLaunchKernelGGL(k_reduce_batch, dim3(2048), dim3(256), 0, stream, hdr, d_res);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -284,7 +284,8 @@ int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl->h_res, c.result_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc(&sl->d_in, c.input_bytes);
     if (e == hipSuccess) e = hipMalloc(&sl->d_res, c.result_bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&sl->d_counter, 2 * sizeof(unsigned int));
+    if (e == hipSuccess)
+      e = hipMalloc((void**)&sl->d_counter, wl::kBatchCounters * sizeof(unsigned int));
     s->slots.push_back(std::move(sl));
     if (e != hipSuccess) {
       wl_server* raw = s.release();

@@ -303,6 +303,51 @@ def test_batch_equals_alone(wl, ctx):
         wl.wl_ensemble_free(ens)
 
 
+def _escalating_requests():
+    """FP32C requests for every field kind and spin on strong fields (eB0 =
+    20, wide tubes, eB0 T up to 200), where the scalar means' FP32 rounding
+    estimates exceed the escalation threshold at about half of the points."""
+    rho = np.array([0.0, 0.4, 1.5])
+    T = np.geomspace(0.5, 10.0, 6)
+    return [dict(kind=k, eB0=20.0, lam=4.0, rho=rho, T=T, spin=sp, precision=0)
+            for k in range(4) for sp in (0, 1)]
+
+
+def test_batch_recomputation_every_variant(wl, ctx):
+    """One compensated-FP32 batch whose requests span all four field kinds
+    and both spins, with points recomputed in FP64 in every scalar request:
+    each request's outputs equal the request evaluated alone, bit for bit,
+    the recomputed means meet the FP64 bar against the oracle and the
+    others their stated estimate; a batch of one request (the smallest
+    result buffer) equals it too."""
+    say("batch recomputation, every variant")
+    x, y = wlinputs.polygon_loops(256, 203, seed=23)
+    ens = wl.wl_ensemble_upload(ctx, x, y, 8)
+    try:
+        reqs = _escalating_requests()
+        outs = wl.wl_average_batch(ctx, ens, reqs, full=True)
+        for q, ob in zip(reqs, outs):
+            say("variant kind", q["kind"], "spin", q["spin"])
+            o1 = wl.wl_average_ex(ctx, ens, wl.field(q["kind"], q["eB0"], q["lam"]),
+                                  q["rho"], q["T"], q["spin"], 0)
+            for k in wl.RESULT_KEYS:
+                assert np.array_equal(ob[k], o1[k], equal_nan=True), (k, q["kind"], q["spin"])
+            o = oracle.evaluate(x, y, q["kind"], q["eB0"], q["lam"], q["rho"], q["T"],
+                                q["spin"], 8, per_loop=True)
+            o_mean, _, _ = oracle.stats(o["group_sums"], 256)
+            m_s, g_s = mean_scales(o["w"], o["spin"], 8, q["spin"])
+            check_fp_err(ob["mean"], o_mean, ob["fp_err"], ob["escalated"], m_s)
+            check_means(0, ob["mean"], ob["group_sums"], o_mean, o["group_sums"], m_s, g_s)
+            if not q["spin"]:
+                assert ob["escalated"].any(), (q["kind"], "no point recomputed")
+        say("batch of one request")
+        one = wl.wl_average_batch(ctx, ens, reqs[2:3], full=True)[0]
+        for k in wl.RESULT_KEYS:
+            assert np.array_equal(one[k], outs[2][k], equal_nan=True), k
+    finally:
+        wl.wl_ensemble_free(ens)
+
+
 def test_server_results_equal_alone(wl, ctx):
     """Continuous batching: requests submitted to the server (several
     batches, graph replays on two slots) give exactly wl_average's result for

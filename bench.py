@@ -70,17 +70,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+VALU_FORMS = ["v_fma_f32 (VOP3, SGPR operand)", "transcendental (rsq, exp, rcp, log)",
+              "v_fma_f64", "mixed: 1 transcendental + 4 v_fma_f32",
+              "v_fmac_f32 (VOP2, VGPRs)", "v_mul_f32 (VOP2, VGPRs)",
+              "v_add_f32 (VOP2, inline constant)", "v_fma_f32 (VOP3, VGPRs)",
+              "v_fma_f32 (VOP3, negated operand)", "v_fmaak_f32 (VOP2, literal)",
+              "v_mul_f32 (VOP2, literal)", "v_fmac_f32 (VOP2, SGPR operand)",
+              "v_exp_f32 (VOP1)", "v_exp_f32 (VOP3, negated operand)"]
+
+
 def valu_rates():
-    """VALU issue rates of the chip from the probe library (FP32 FMA,
-    transcendental, FP64 FMA wave-instructions per second over all CUs)."""
+    """VALU issue rates of the chip from the probe library: wave-instructions
+    per second over all CUs for each instruction form of VALU_FORMS."""
     import ctypes
 
     import torch
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1407_7486_amd", "libwl_probe.so"))
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    rates = (ctypes.c_double * 7)()
-    ms = (ctypes.c_double * 7)()
-    rc = lib.wl_probe_valu_rates(ctypes.c_int(n_cu), ctypes.c_int(3), rates, ms)
+    n = len(VALU_FORMS)
+    rates = (ctypes.c_double * n)()
+    ms = (ctypes.c_double * n)()
+    rc = lib.wl_probe_valu_rates(ctypes.c_int(n_cu), ctypes.c_int(3), ctypes.c_int(n), rates,
+                                 ms)
     if rc != 0:
         raise RuntimeError(f"VALU probe failed with HIP error {rc}")
     clock = 2.4e9
@@ -88,19 +99,18 @@ def valu_rates():
     # the mixed stream (1 transcendental : 4 FMA) takes, per 5 instructions,
     # this share of the time its parts take at their separate rates
     mix_share = (5.0 / rates[3]) / (1.0 / rates[1] + 4.0 / rates[0])
-    out = {"n_cu": n_cu, "fp32_fma_wave_insts_per_s": rates[0],
-           "trans_wave_insts_per_s": rates[1], "fp64_fma_wave_insts_per_s": rates[2],
-           "mix_wave_insts_per_s": rates[3], "mix_time_over_sum_of_parts": mix_share,
-           "fmac_vop2_wave_insts_per_s": rates[4], "mul_vop2_wave_insts_per_s": rates[5],
-           "add_vop2_wave_insts_per_s": rates[6],
-           "ms": list(ms),
-           # cycles per wave-instruction per SIMD at the 2.4 GHz peak clock
-           "cycles_per_inst_at_2.4GHz": [simds * clock / r for r in rates],
-           "fp32_fma_lane_ops_per_s": 64 * rates[0]}
+    forms = [{"form": f, "wave_insts_per_s": r, "cycles_at_2.4GHz": simds * clock / r,
+              "ms": m} for f, r, m in zip(VALU_FORMS, rates, ms)]
+    out = {"n_cu": n_cu, "forms": forms, "mix_time_over_sum_of_parts": mix_share,
+           "fp32_fmac_lane_ops_per_s": 64 * rates[4]}
     print(json.dumps(out), flush=True)
-    print(f"rates: fp32={rates[0]:.6e} trans={rates[1]:.6e} fp64={rates[2]:.6e} "
-          f"mix={rates[3]:.6e} fmac={rates[4]:.6e} mul={rates[5]:.6e} add={rates[6]:.6e}",
-          flush=True)
+    for f in forms:
+        print(f"{f['form']:40s} {f['wave_insts_per_s']:.4e}/s {f['cycles_at_2.4GHz']:5.2f} cycles",
+              flush=True)
+    # fp32: the fastest FP32 form measured (so that issue times priced with
+    # it are lower bounds)
+    fast = max(rates[k] for k in (0, 4, 5, 6, 7, 8, 9, 10, 11))
+    print(f"rates: fp32={fast:.6e} trans={rates[1]:.6e} fp64={rates[2]:.6e}", flush=True)
 
 
 def copy_calibration(nbytes):
@@ -147,12 +157,15 @@ def serve_run(wl, ctx, rate, n_requests, nl):
             time.sleep(ta - now)
         q["precision"] = wl.WL_FP32C
         tickets.append((srv.submit(q), time.perf_counter() - t0))
-    lat, esc = [], 0
+    lat, que, svc, esc = [], [], [], 0
     for t, ts in tickets:
         st, ms = srv.wait(t, 600.0)
         if st != 0:
             raise RuntimeError(f"serving request failed with status {st}")
         lat.append(ms)
+        q_ms, s_ms = srv.timing(t)
+        que.append(q_ms)
+        svc.append(s_ms)
         esc += int(srv.result(t, full=True)["escalated"].sum())
     t_end = time.perf_counter() - t0
     info = srv.info()
@@ -164,11 +177,38 @@ def serve_run(wl, ctx, rate, n_requests, nl):
     out = {"requests": len(reqs), "offered_rate": rate,
            "achieved_rate": len(reqs) / t_end, "n_loops": nl, "n_ppl": n_ppl,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "queue_p50_ms": float(np.percentile(que, 50)),
+           "service_p50_ms": float(np.percentile(svc, 50)),
+           "service_p99_ms": float(np.percentile(svc, 99)),
            "segment_evals_per_s": segs / t_end, "wall_s": t_end,
-           "batches": info["batches"], "slots": 2, "escalated_fraction": esc / pts}
-    log(f"[bench] serve at {rate}/s: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms, "
-        f"{out['segment_evals_per_s']:.3e} seg/s, {info['batches']} batches")
+           "batches": info["batches"], "requests_per_batch": len(reqs) / info["batches"],
+           "slots": 2, "escalated_fraction": esc / pts}
+    log(f"[bench] serve at {rate}/s: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms "
+        f"(queued p50 {out['queue_p50_ms']:.1f} ms, service p50 {out['service_p50_ms']:.1f} "
+        f"ms), {out['achieved_rate']:.2f} req/s, {out['segment_evals_per_s']:.3e} seg/s, "
+        f"{info['batches']} batches")
     return out
+
+
+# (loops, [(offered rate per s, requests)]): at each size one or two rates
+# below the capacity measured there (about 11, 2.9 and 0.7 requests/s at
+# 16384, 65536 and 262144 loops) and one far above it
+SERVE_SWEEP = [(16384, [(2.0, 12), (6.0, 24), (50.0, 48)]),
+               (65536, [(0.7, 8), (1.8, 12), (20.0, 24)]),
+               (262144, [(0.25, 6), (5.0, 12)])]
+
+
+def serve_sweep():
+    """Serving points of SERVE_SWEEP, one JSON line each."""
+    import torch
+
+    import paper_1407_7486_amd as wl
+    ctx = wl.wl_create(0, torch.cuda.current_stream().cuda_stream)
+    for nl, points in SERVE_SWEEP:
+        for rate, n in points:
+            out = serve_run(wl, ctx, rate, n, nl)
+            print(json.dumps({"serve_point": out}), flush=True)
+    wl.wl_destroy(ctx)
 
 
 def c3_run(wl, ctx, torch, dev, precision_report):
@@ -305,6 +345,10 @@ def main():
     ap.add_argument("--no-c3", dest="c3", action="store_false",
                     help="skip the precision-stress evaluation (131072 x 8192 loops, "
                          "32 x 48 grid, sech^2 B0 = 20, lambda = 4, spinor)")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only the serving sweep: offered rates below and above capacity "
+                         "on ensembles of 16384, 65536 and 262144 loops (prints one JSON "
+                         "line per point) and exit")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving run (prints its JSON) and exit")
     ap.add_argument("--batch-requests", type=int, default=0,
@@ -326,6 +370,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU split is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.serve_sweep:
+        serve_sweep()
+        return
     if args.serve_only:
         import torch
 

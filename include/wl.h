@@ -331,6 +331,15 @@ int wl_server_poll(wl_server* srv, int64_t ticket, int32_t* status, double* late
 int wl_server_wait(wl_server* srv, int64_t ticket, double timeout_s, int32_t* status,
                    double* latency_ms);
 
+/* Where a finished ticket's latency went: queue_ms from submission to the
+ * launch of its batch, service_ms from that launch to its completion (the
+ * batch's device work, the copy of its results and the hand-back; with
+ * two slots the batch may share the GPU with the other slot's).  Both -1
+ * while the ticket is queued or running, or if it finished without a
+ * launch (an empty grid, or a failure before its batch started).
+ * Returns WL_EINVAL for an unknown ticket or NULL outputs. */
+int wl_server_timing(wl_server* srv, int64_t ticket, double* queue_ms, double* service_ms);
+
 /* Forget a finished ticket. */
 int wl_server_release(wl_server* srv, int64_t ticket);
 

@@ -34,7 +34,7 @@ EXPORTS = (
     "wl_average", "wl_average_async", "wl_per_loop", "wl_set_timing",
     "wl_last_kernel_ms", "wl_kernel_ms_total", "wl_average_batch",
     "wl_server_create", "wl_server_submit", "wl_server_poll", "wl_server_wait",
-    "wl_server_release", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
+    "wl_server_release", "wl_server_timing", "wl_server_info", "wl_server_last_error", "wl_server_destroy",
     "wl_discretisation", "wl_subloop_per_loop", "wl_action_grids", "wl_action",
     "wl_ensemble_generate", "wl_ensemble_download", "wl_ensemble_set_groups",
     "wl_correlation", "wl_regroup", "wl_average_async_noalloc", "wl_average_ex",
@@ -144,6 +144,7 @@ _sigs = {
     "wl_server_poll": ([_vp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_d)], ctypes.c_int),
     "wl_server_wait": ([_vp, _i64, _d, ctypes.POINTER(_i32), ctypes.POINTER(_d)], ctypes.c_int),
     "wl_server_release": ([_vp, _i64], ctypes.c_int),
+    "wl_server_timing": ([_vp, _i64, ctypes.POINTER(_d), ctypes.POINTER(_d)], ctypes.c_int),
     "wl_server_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
                        ctypes.c_int),
     "wl_server_last_error": ([_vp], ctypes.c_char_p),
@@ -482,6 +483,13 @@ class Server:
         self._check(_lib.wl_server_wait(self.h, ticket, float(timeout_s), ctypes.byref(st),
                                         ctypes.byref(lat)))
         return st.value, lat.value
+
+    def timing(self, ticket):
+        """(queue_ms, service_ms) of a finished ticket: submission to its
+        batch's launch, launch to completion (-1, -1 if it did not run)."""
+        q, sv = _d(), _d()
+        self._check(_lib.wl_server_timing(self.h, ticket, ctypes.byref(q), ctypes.byref(sv)))
+        return q.value, sv.value
 
     def result(self, ticket, release=True, full=False):
         """(mean, err, group_sums) of a finished ticket, or with full=True the

@@ -41,7 +41,7 @@ struct Ticket {
   wl::FieldArgs fa{};
   wl::ReqPlan plan;
   int32_t state = 1;  // 1 queued, 2 running, 0 done, < 0 error
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_launch, t_done;
 };
 
 struct Slot {
@@ -181,6 +181,10 @@ hipError_t launch_slot(wl_server* s, Slot* sl) {
     return hipErrorInvalidValue;  // admission guarantees the fit
   hipError_t e = hipSuccess;
   if (!sl->exec[sl->prec]) e = capture(s, sl, sl->prec);
+  // read under the lock only once the ticket is done (its state is set
+  // under the lock after this)
+  const Clock::time_point now = Clock::now();
+  for (Ticket* t : sl->reqs) t->t_launch = now;
   if (e == hipSuccess) e = hipGraphLaunch(sl->exec[sl->prec], sl->stream);
   const size_t out_b = sl->lay.head_bytes;
   if (e == hipSuccess)
@@ -372,6 +376,20 @@ int wl_server_wait(wl_server* s, int64_t ticket, double timeout_s, int32_t* stat
     *latency_ms = (t->state <= 0)
                       ? std::chrono::duration<double, std::milli>(t->t_done - t->t_submit).count()
                       : -1.0;
+  return WL_OK;
+}
+
+int wl_server_timing(wl_server* s, int64_t ticket, double* queue_ms, double* service_ms) {
+  if (!s || !queue_ms || !service_ms) return WL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return sfail(s, WL_EINVAL, "unknown ticket %lld", (long long)ticket);
+  const Ticket* t = it->second.get();
+  using Ms = std::chrono::duration<double, std::milli>;
+  // (a request with no grid points finishes without a launch)
+  const bool ran = t->state <= 0 && t->t_launch >= t->t_submit;
+  *queue_ms = ran ? Ms(t->t_launch - t->t_submit).count() : -1.0;
+  *service_ms = ran ? Ms(t->t_done - t->t_launch).count() : -1.0;
   return WL_OK;
 }
 

@@ -368,6 +368,10 @@ def test_server_results_equal_alone(wl, ctx):
             for t in tickets:
                 st, lat = srv.wait(t, 120.0)
                 assert st == 0 and lat >= 0
+                # latency = time queued + service time (one clock, so the
+                # parts add up to the whole up to rounding)
+                qms, sms = srv.timing(t)
+                assert qms >= 0 and sms > 0 and abs(qms + sms - lat) <= 1e-6 * max(1.0, lat)
             info = srv.info()
             assert info["batches"] >= 5 and info["pending"] == 0
             for q, t in zip(reqs, tickets):

@@ -189,9 +189,16 @@ int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
  *                              of the mean, and the mean's rounding
  *                              tolerance is 1e-6 M_S.
  *   fp_err     [n_rho][n_T]    estimated rounding error of the mean: from
- *                              each loop's phase-sum rounding, 32 u
- *                              sqrt(sum_i t_i^2) over its segment terms t_i,
- *                              carried to the mean through sin(Phi) cosh(S)
+ *                              each loop's phase-sum rounding, 32 u l_2,
+ *                              l_2 = |c_Phi| sqrt(mean_i q_i^2) (T |c| +
+ *                              rho_cm sqrt(T) |d_y|) over its segments (the
+ *                              field weights q_i sampled every 8 segments,
+ *                              |c|, |d_y| the loop's Euclidean norms of the
+ *                              cross product's two parts, which are summed
+ *                              apart; with even weights l_2 bounds the
+ *                              parts' rounding sizes sqrt(sum_i e_i^2) of
+ *                              wl_per_loop), carried to the mean
+ *                              through sin(Phi) cosh(S)
  *                              and added in quadrature, plus 8 u M_S for the
  *                              roundings shared by all loops (u = 2^-24 for
  *                              the FP32 modes, 2^-53 for FP64 and for
@@ -358,8 +365,12 @@ int wl_server_destroy(wl_server* srv);
  *   spin_exp  S = e int_0^T B dtau (0 is written when spin == 0)
  *   w         cos(Phi) * (spin ? cosh(S) : 1)
  * WL_FP32C: a (loop, point) whose estimated FP32 phase rounding, 32 u
- * sqrt(sum_i t_i^2) over its segment terms t_i, exceeds the phase tolerance
- * 1e-5 max(1, |Phi|) is recomputed in FP64 (all three values).
+ * sqrt(sum_i e_i^2), exceeds the phase tolerance 1e-5 max(1, |Phi|) is
+ * recomputed in FP64 (all three values); e_i is the size of segment i's
+ * rounding relative to u, (|T c_i| + |rho_cm sqrt(T) d_y,i|) q_i: the
+ * cross product's two parts (Sec. 3.2.1) are summed apart, and q_i is the
+ * field weight or, where the weight is the difference of two larger parts
+ * (sech^2 and Gaussian beyond rho = lambda/2), the parts' size.
  * n_loops * n_rho * n_T must not exceed 2^27.
  * Synchronous.  Errors: WL_EINVAL, WL_ENOMEM, WL_EHIP. */
 int wl_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,

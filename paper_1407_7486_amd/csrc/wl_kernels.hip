@@ -85,14 +85,19 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
 //   GAUSS  qa = 2g/(eB0 lambda^2)   qb = b/eB0
 //   RATIONAL qa = 1/(lambda^2+rho^2) qb = qa^2
 // r2 > 0 (the caller adds 1e-30).
+// qe: the scale of qa's rounding error, qa itself except where qa is formed
+// as the difference of two larger parts (the far branches of sech^2 and the
+// Gaussian, 1/r2 times 1 - hp or 1 - E): there the parts' size 1/r2, since
+// their rounding, relative to them, carries over to the difference.
 template <int KIND, bool COMP>
 __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
-                                          float& qa, float& qb) {
+                                          float& qa, float& qb, float& qe) {
   if constexpr (KIND == kConst) {
     (void)r2;
     (void)f;
     qa = 1.0f;
     qb = 1.0f;
+    qe = 1.0f;
   } else if constexpr (KIND == kSech2) {
     // r2 is in scaled units, r2 = t^2 with t = 2 u log2(e) and u = rho/lambda
     // (the geometry multiplied by gs = 2 log2(e)/lambda).  Then E = exp(-2u)
@@ -119,11 +124,13 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
       asm volatile("");
       const float v = r2 * kSech2Vs;
       qa = horner_f32<WL_Q_SECH2_F32_DEG>(WL_Q_SECH2_F32, v) * kSech2Ps;
+      qe = qa;
     } else {
       // qa = (1 - hp) q^2 with hp = log2(1+E) + t E/(1+E), q^2 = 1/r2
       const float hp = fmaf(t, Eip, __builtin_amdgcn_logf(opE));
       const float q2 = q * q;
       qa = fmaf(-hp, q2, q2);
+      qe = q2;
     }
   } else if constexpr (KIND == kGauss) {
     // v = rho^2/lambda^2, E = exp(-v); 2 g/eB0 = (1-E)/v (polynomial
@@ -136,13 +143,16 @@ __device__ __forceinline__ void field_f32(float r2, const FieldArgs& f,
       asm volatile("");
       const float v = r2 * f.inv_lam2;
       qa = horner_f32<WL_P_GAUSS_F32_DEG>(WL_P_GAUSS_F32, v) * f.inv_lam2;
+      qe = qa;
     } else {
-      qa = (1.0f - E) * __builtin_amdgcn_rcpf(r2);
+      qe = __builtin_amdgcn_rcpf(r2);
+      qa = (1.0f - E) * qe;
     }
   } else {  // kRational
     const float r = __builtin_amdgcn_rcpf(COMP ? (r2 + f.lam2) + f.lam2_lo : r2 + f.lam2);
     qa = r;
     qb = r * r;
+    qe = r;
   }
 }
 
@@ -281,7 +291,10 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
 //   EST 1  Q ~ sum_i qa_i^2, sampled from the first segment of every fetch
 //          of 8 (each sample standing for 8 segments; tail segments counted
 //          singly), two FMAs per 8 segments;
-//   EST 2  Q = sum_i (cross_i qa_i)^2 exactly (in the units of A).
+//   EST 2  Q = sum_i ((|R c_i| + |U d_y,i|) qe_i)^2 exactly (in the units
+//          of A), qe_i the scale of qa_i's rounding (field_f32): the
+//          squared size of each term's rounding relative to u, the two
+//          parts of the cross product being summed apart.
 template <int KIND, bool SPIN, bool COMP, int EST = 0>
 __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               int32_t n, const LaneF32& c,
@@ -310,8 +323,8 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
     } else {
       r2 = 1.0f;
     }
-    float qa, qb;
-    field_f32<KIND, COMP>(r2, f, qa, qb);
+    float qa, qb, qe;
+    field_f32<KIND, COMP>(r2, f, qa, qb, qe);
     p.c = fmaf(s.w, qa, p.c);
     p.d = fmaf(s.z, qa, p.d);
     if constexpr (kSpinSum) p.b += qb;
@@ -319,7 +332,9 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
       if (sample == 1) qs = fmaf(qa, qa, qs);
       if (sample == 2) qs = fmaf(qa * 0.125f, qa, qs);
     } else if constexpr (EST == 2) {
-      const float x = fmaf(Rf, s.w, Uf * s.z) * qa;
+      // the cross product's two parts are summed apart, each carrying
+      // rounding of its own size
+      const float x = (fabsf(Rf * s.w) + fabsf(Uf * s.z)) * qe;
       qs = fmaf(x, x, qs);
     }
   };
@@ -1279,8 +1294,13 @@ __global__ void k_zero_u32(unsigned int* __restrict__ p) { p[threadIdx.x] = 0u; 
 // Per-loop values of the (sub-)loop that takes, within each loop of the
 // ensemble, segments seg_off .. seg_off+m-1 of `seg` (FP32 paths) or of
 // `seg64` (FP64 path).  Compensated FP32: each lane's phase carries the
-// rounding estimate kPhaseK u sqrt(sum_i t_i^2) (exact sum of the squared
-// segment terms); where it exceeds the phase tolerance 1e-5 max(1, |Phi|)
+// rounding estimate kPhaseK u sqrt(sum_i e_i^2) over its segment terms,
+// e_i = (|R c_i| + |U d_y,i|) qe_i the size of term i's rounding relative
+// to u: the cross product's parts R c_i and U d_y,i are summed apart (and
+// cancel where a loop crosses the axis far from its centre), and qe_i is
+// qa_i or, where qa_i is the difference of two larger parts, their size
+// (field_f32); where it exceeds the phase tolerance
+// 1e-5 max(1, |Phi|)
 // the lane's phase, spin exponent and w are recomputed in FP64 from the raw
 // points (the whole wave walks the loop when any lane is flagged).
 template <int KIND, bool SPIN, int PREC>

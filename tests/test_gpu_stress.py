@@ -46,7 +46,7 @@ def group_sums(w):
 
 def test_precision_stress_table(setup):
     wl, ctx, ens, x, y = setup
-    rows = []
+    rows, fails = [], []
     worst = {"fp32c_mean": 0.0, "fp32c_fperr": 0.0, "fp64_mean": 0.0}
     for fcfg in wlinputs.stress_fields():
         stride = 1 if fcfg["lam"] == 4.0 else STRIDE
@@ -75,19 +75,27 @@ def test_precision_stress_table(setup):
                 dm = np.abs(r["mean"] - o_mean)
                 row += [float(rel.max()), float((rel > 1e-5).mean()), e_sp,
                         float((dm / m_s).max())]
+                case = (fcfg["eB0"], fcfg["lam"], spin)
                 if prec == 0:
-                    # the stated bars, no conditioning terms
-                    assert (rel <= 1e-5).all(), (fcfg, spin, float(rel.max()))
-                    if spin:
-                        assert e_sp <= 1e-5, (fcfg, spin, e_sp)
+                    # the stated bars, no conditioning terms (checked after
+                    # the table is printed)
+                    if not (rel <= 1e-5).all():
+                        fails.append((case, "fp32c phase", float(rel.max()),
+                                      int((rel > 1e-5).sum())))
+                    if spin and e_sp > 1e-5:
+                        fails.append((case, "fp32c spin exponent", e_sp, 0))
                     worst["fp32c_mean"] = max(worst["fp32c_mean"], float((dm / m_s).max()))
-                    worst["fp32c_fperr"] = max(worst["fp32c_fperr"],
-                                               check_fp_err(r["mean"], o_mean, r["fp_err"],
-                                                            r["escalated"], m_s))
+                    try:
+                        worst["fp32c_fperr"] = max(
+                            worst["fp32c_fperr"],
+                            check_fp_err(r["mean"], o_mean, r["fp_err"], r["escalated"], m_s))
+                    except AssertionError as e:
+                        fails.append((case, "fp32c stated estimate", str(e), 0))
                     np.testing.assert_allclose(r["scale"], m_s, rtol=1e-3)
                 elif prec == 2:
                     lim = phase_limit(2, o_ph, o1["phase_sq"], o1["phase_abs"])
-                    assert (dph <= lim).all(), (fcfg, spin, float((dph / lim).max()))
+                    if not (dph <= lim).all():
+                        fails.append((case, "fp64 phase", float((dph / lim).max()), 0))
                     # both sides round each segment term by a few u: the mean
                     # inherits sin(Phi) cosh(S) times that, added over loops
                     ch = np.cosh(o_sp)
@@ -113,5 +121,8 @@ def test_precision_stress_table(setup):
     print(f"worst: fp32c mean error / 1e-6 M_S {worst['fp32c_mean'] / 1e-6:.3g}, "
           f"fp32c mean error / stated estimate {worst['fp32c_fperr']:.3g}, "
           f"fp64 mean error / tolerance {worst['fp64_mean']:.3g}")
+    for f in fails:
+        print("FAILED BAR", f)
     sys.stdout.flush()
+    assert not fails, fails
     assert worst["fp32c_mean"] <= 1e-6 and worst["fp64_mean"] <= 1.0

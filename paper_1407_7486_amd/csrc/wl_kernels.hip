@@ -750,16 +750,30 @@ __device__ __forceinline__ void run_item(const float4* __restrict__ seg,
   }
 }
 
+// A value every lane of the wave holds, moved to scalar registers, so that
+// branches on it are taken by the whole wave.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // The FP64 recomputation of the flagged grid points, in work items (row gs
 // = g n_sub + sub of the evaluation's partial sums, chunk c of the flagged
 // points): the sub-range's loops are walked in FP64 from the raw points
-// (loop_sums_f64raw, the FP64 path's arithmetic, each loop's points coming
-// in through scalar loads that the whole wave shares) for the flagged
-// points list[64 c .. 64 c + 63] (ascending, cnt of them), one per lane,
-// and each point's sum of w over the sub-range is written over the item's
-// FP32 partial sum.  Items are numbered chunk-major, k = c rows + gs
-// (rows = G n_sub), so that the items of a small count, one chunk, lie
-// side by side and spread over every XCD and compute unit.
+// (loop_sums_f64raw, the FP64 path's arithmetic) for the flagged points
+// list[64 c .. 64 c + 63] (ascending, cnt of them), and each point's sum of
+// w over the sub-range is written over the item's FP32 partial sum.  A
+// chunk of more than 32 points takes one per lane, the wave walking each
+// loop together (its points come in through scalar loads that the wave
+// shares).  A chunk of at most 32 (16) points leaves lanes free: the wave's
+// lanes then form 2 (4) copies of the chunk, copy r walking loops l0 + r,
+// l0 + r + 2 (4), ... through vector loads (2 or 4 loops per wave, so a
+// load touches at most 4 cache lines), and a fixed butterfly adds the
+// copies' sums.  Items are numbered chunk-major, k = c rows + gs (rows =
+// G n_sub), so that the items of a small count, one chunk, lie side by side
+// and spread over every XCD and compute unit.  The split depends only on
+// the count, so a request gives the same bits alone and in a batch.
 constexpr int kEscWaves = 3;  // waves per SIMD of the recomputation kernels
 __device__ __forceinline__ int64_t esc_items(int64_t rows, int32_t cnt) {
   return rows * (((int64_t)cnt + kWave - 1) / kWave);
@@ -781,20 +795,38 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
   const int64_t l0 = g * loops_per_group + (gs % n_sub) * loops_per_sub;
   int64_t l1 = l0 + loops_per_sub;
   if (l1 > (g + 1) * loops_per_group) l1 = (g + 1) * loops_per_group;
-  const int32_t j = chunk * kWave + (int32_t)(threadIdx.x % kWave);
-  const bool esc = j < cnt;
-  const int32_t pg = list[esc ? j : cnt - 1];
+  const int32_t lane = (int32_t)(threadIdx.x % kWave);
+  const int32_t cnt_c = min(kWave, cnt - chunk * kWave);  // wave-uniform
+  const int32_t P = cnt_c <= 16 ? 16 : cnt_c <= 32 ? 32 : kWave;
+  const int32_t p = lane % P, r = lane / P;
+  const bool esc = p < cnt_c;
+  const int32_t pg = list[chunk * kWave + (esc ? p : cnt_c - 1)];
   const double rho = rho_g[pg / n_T];
   const double T = T_g[pg % n_T];
   const double s = sqrt(T);
   double acc = 0.0;
-  for (int64_t l = l0; l < l1; ++l) {
-    double A, B, phi, S;
-    loop_sums_f64raw<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, 0, 1, n_ppl, rho, s,
-                                 f, A, B);
-    acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
+  if (P == kWave) {
+    for (int64_t l = l0; l < l1; ++l) {
+      double A, B, phi, S;
+      // (wave_uniform keeps the compiler from merging this walk with the
+      // copies' below, which would make these loads vector loads)
+      const int64_t lu = wave_uniform(l);
+      loop_sums_f64raw<KIND, SPIN>(X + lu * n_ppl, Y + lu * n_ppl, n_ppl, 0, 1, n_ppl, rho,
+                                   s, f, A, B);
+      acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
+    }
+  } else {
+    const int32_t R = kWave / P;
+    for (int64_t l = l0 + r; l < l1; l += R) {
+      double A, B, phi, S;
+      loop_sums_f64raw<KIND, SPIN>(X + l * n_ppl, Y + l * n_ppl, n_ppl, 0, 1, n_ppl, rho, s,
+                                   f, A, B);
+      acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
+    }
+    if (P == 16) acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
   }
-  if (esc) out[gs * n_pts + pg] = acc;
+  if (esc && r == 0) out[gs * n_pts + pg] = acc;
 }
 
 // The flagged grid points of one evaluation in ascending order, list[0 ..
@@ -1062,14 +1094,6 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 6))) void k_disc(
 __device__ __forceinline__ int64_t take_item(unsigned int* counter) {
   const unsigned int t = atomicAdd(counter, threadIdx.x % kWave == 0 ? 1u : 0u);
   return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-}
-
-// A value every lane of the wave holds, moved to scalar registers, so that
-// branches on it are taken by the whole wave.
-__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Batched evaluation of uneven requests in one persistent launch.  Items of

@@ -649,7 +649,13 @@ def main():
         "config": {"workload": args.workload, "n_loops": cfg["n_loops"],
                    "n_ppl": cfg["n_ppl"], "n_rho": int(rho.size), "n_T": int(T.size),
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
-                   "spin": spin, "precision": "fp32c", "generator": "d-loops, seed 0"},
+                   "spin": spin, "precision": "fp32c",
+                   "precision_note": "FP32 segment arithmetic; each 32-segment block summed "
+                                     "in FP32 and the block sums in FP64 (in place of FP32 "
+                                     "Kahan summation); FP64 epilogue and group sums; loops "
+                                     "and means the rounding estimate cannot bring within "
+                                     "1e-5 (phase) and 1e-6 M_S (mean) recomputed in FP64",
+                   "generator": "d-loops, seed 0"},
         "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "c3": c3, "c4": c4,
         "serve": serve,
         "serve_sub_capacity": serve_low, "disc": disc, "generate": gen, "correlation": corr,

@@ -380,6 +380,9 @@ def test_server_results_equal_alone(wl, ctx):
                                       q["rho"], q["T"], q["spin"], q["precision"])
                 for k in wl.RESULT_KEYS:
                     assert np.array_equal(ob[k], o1[k], equal_nan=True), (k, q)
+            with pytest.raises(wl.WLError) as ei:
+                srv.timing(10 ** 9)
+            assert ei.value.code == wl.WL_EINVAL
             big = dict(kind=1, eB0=1.0, lam=1.0, rho=np.linspace(0, 3, 128),
                        T=np.geomspace(1e-3, 10, 64), spin=1, precision=0)
             with pytest.raises(wl.WLError) as ei:

@@ -281,6 +281,24 @@ def committed_issue_frac(workload, kernel_ms):
     return sum(a / b for a, b in zip(n, r)) / (kernel_ms * 1e-3)
 
 
+def committed_lane_op_frac(workload, kernel_ms):
+    """Raw VALU lane-operation rate of the main kernel against the published
+    FP32 peak counted in lane-operations (157.3e12 / 2: one per lane and
+    cycle for a two-flop FMA): 64 x (the wave-instructions per launch of
+    profiles/k_average_<workload>.md, every class counted once) over the
+    kernel's duration.  None when the counters are stale."""
+    import re
+    p1 = os.path.join(PROFILES, f"k_average_{workload}.md")
+    if not os.path.exists(p1):
+        return None
+    m1 = re.search(r"valu: fp32=([\d.e+]+) trans=([\d.e+]+) fp64=([\d.e+]+) "
+                   r"source=([0-9a-f]+)", open(p1).read())
+    if not m1 or m1.group(4) != kernel_source_hash():
+        return None
+    insts = sum(float(v) for v in m1.groups()[:3])
+    return 64.0 * insts / (kernel_ms * 1e-3) / (PEAK_FP32 / 2.0)
+
+
 def batch_run(args):
     """Uneven requests (sech^2 or Gaussian tube, eB0 ~ U[0.5,10], lambda ~
     U[0.2,5], N_rho ~ U{4..128}, N_T ~ U{8..64}, spin 50/50, FP32C; seed 1)
@@ -569,7 +587,8 @@ def main():
                 "frac": achieved / PEAK_FP32, "traffic": traffic,
                 "traffic_source_hash": traffic_src, "kernel_source_hash": kernel_source_hash(),
                 "kernel": f"k_average<{kname},spin={spin},fp32c>", "kernel_ms": k_ms,
-                "ops_per_segment": slots, "issue_frac": issue}
+                "ops_per_segment": slots, "issue_frac": issue,
+                "valu_lane_op_frac": committed_lane_op_frac(args.workload, k_ms)}
 
     c3 = None
     if args.c3:

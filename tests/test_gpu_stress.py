@@ -126,3 +126,28 @@ def test_precision_stress_table(setup):
     sys.stdout.flush()
     assert not fails, fails
     assert worst["fp32c_mean"] <= 1e-6 and worst["fp64_mean"] <= 1.0
+
+
+def test_cross_product_cancellation_corner(setup):
+    """The corner of the narrow strong tube (sech^2 B0 = 20, lambda = 0.25,
+    rho_cm 3.5-5, T 5.6-10) where loops cross the axis far from their
+    centre, so that the cross product's two parts, summed apart, cancel
+    within segments (up to ~23x the term): every compensated-FP32 per-loop
+    phase meets 1e-5 max(1, |Phi|), and loop 108 at rho_cm = 4.03, T = 10,
+    whose FP32 error there is 96 u sqrt(sum_i t_i^2), is recomputed in FP64
+    (its value equals the FP64 path's)."""
+    wl, ctx, ens, x, y = setup
+    f = [c for c in wlinputs.stress_fields() if c["eB0"] == 20.0 and c["lam"] == 0.25][0]
+    rho = wlinputs.rho_grid(*f["rho"])[22:32]
+    T = wlinputs.t_grid(*f["T"])[44:48]
+    print("[case] cancellation corner oracle", flush=True)
+    o = oracle.evaluate(x, y, 1, 20.0, 0.25, rho, T, 0, G, per_loop=True)
+    fld = wl.field(1, 20.0, 0.25)
+    print("[case] cancellation corner per-loop FP32C / FP64", flush=True)
+    ph, _, _ = wl.wl_per_loop(ctx, ens, fld, rho, T, 0, 0, 0, N_LOOPS)
+    ph64, _, _ = wl.wl_per_loop(ctx, ens, fld, rho, T, 0, 2, 0, N_LOOPS)
+    rel = np.abs(ph - o["phase"]) / np.maximum(1, np.abs(o["phase"]))
+    print(f"worst FP32C per-loop phase error {rel.max():.3g}; recomputed "
+          f"{float((ph == ph64).mean()):.3f} of the values", flush=True)
+    assert (rel <= 1e-5).all(), float(rel.max())
+    assert ph[108, 3, 3] == ph64[108, 3, 3]

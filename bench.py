@@ -129,7 +129,7 @@ def copy_calibration(nbytes):
                       "GBps_read_plus_write": 2 * 4 * n / dt / 1e9}), flush=True)
 
 
-def serve_run(wl, ctx, rate, n_requests, nl):
+def serve_run(wl, ctx, rate, n_requests, nl, in_order=False):
     """Bounded serving run: Poisson arrivals at `rate` per second of
     n_requests uneven requests (sech^2 or Gaussian tube, eB0 ~ U[0.5,10],
     lambda ~ U[0.2,5], N_rho ~ U{4..128}, N_T ~ U{8..64}, spin 50/50, FP32C;
@@ -147,8 +147,9 @@ def serve_run(wl, ctx, rate, n_requests, nl):
     reqs = wlinputs.draw_requests(n_requests, seed=1)
     rng = np.random.Generator(np.random.Philox(key=2))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
-    srv = wl.Server(ctx, ens, slots=2)
-    log(f"[bench] serve: {len(reqs)} requests at {rate}/s on {nl} loops")
+    srv = wl.Server(ctx, ens, slots=2, in_order=in_order)
+    mode = "in order" if in_order else "overlapping"
+    log(f"[bench] serve: {len(reqs)} requests at {rate}/s on {nl} loops, slots {mode}")
     t0 = time.perf_counter()
     tickets = []
     for q, ta in zip(reqs, arrivals):
@@ -182,20 +183,24 @@ def serve_run(wl, ctx, rate, n_requests, nl):
            "service_p99_ms": float(np.percentile(svc, 99)),
            "segment_evals_per_s": segs / t_end, "wall_s": t_end,
            "batches": info["batches"], "requests_per_batch": len(reqs) / info["batches"],
-           "slots": 2, "escalated_fraction": esc / pts}
-    log(f"[bench] serve at {rate}/s: p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms "
+           "slots": 2, "in_order": bool(in_order), "escalated_fraction": esc / pts}
+    log(f"[bench] serve at {rate}/s ({mode}): p50 {out['p50_ms']:.1f} ms p99 {out['p99_ms']:.1f} ms "
         f"(queued p50 {out['queue_p50_ms']:.1f} ms, service p50 {out['service_p50_ms']:.1f} "
         f"ms), {out['achieved_rate']:.2f} req/s, {out['segment_evals_per_s']:.3e} seg/s, "
         f"{info['batches']} batches")
     return out
 
 
-# (loops, [(offered rate per s, requests)]): at each size one or two rates
-# below the capacity measured there (about 11, 2.9 and 0.7 requests/s at
-# 16384, 65536 and 262144 loops) and one far above it
-SERVE_SWEEP = [(16384, [(2.0, 12), (6.0, 24), (50.0, 48)]),
-               (65536, [(0.7, 8), (1.8, 12), (20.0, 24)]),
-               (262144, [(0.25, 6), (5.0, 12)])]
+# (loops, [(offered rate per s, requests, in-order slots)]): at each size
+# one or two rates below the capacity measured there (about 11, 3.4 and 0.8
+# requests/s at 16384, 65536 and 262144 loops) and one far above it, with
+# the server's default overlapping slots; the points near and above
+# capacity again with in-order slots
+SERVE_SWEEP = [(16384, [(2.0, 12, False), (6.0, 24, False), (50.0, 48, False),
+                        (6.0, 24, True), (50.0, 48, True)]),
+               (65536, [(0.7, 8, False), (1.8, 12, False), (20.0, 24, False),
+                        (1.8, 12, True), (20.0, 24, True)]),
+               (262144, [(0.25, 6, False), (5.0, 12, False), (5.0, 12, True)])]
 
 
 def serve_sweep():
@@ -205,8 +210,8 @@ def serve_sweep():
     import paper_1407_7486_amd as wl
     ctx = wl.wl_create(0, torch.cuda.current_stream().cuda_stream)
     for nl, points in SERVE_SWEEP:
-        for rate, n in points:
-            out = serve_run(wl, ctx, rate, n, nl)
+        for rate, n, in_order in points:
+            out = serve_run(wl, ctx, rate, n, nl, in_order)
             print(json.dumps({"serve_point": out}), flush=True)
     wl.wl_destroy(ctx)
 

@@ -314,6 +314,14 @@ typedef struct wl_server_config {
   int32_t max_batch;   /* requests per batch (default 1024)                 */
   size_t input_bytes;  /* per slot (default 8 MiB)                          */
   size_t result_bytes; /* per slot (default 512 MiB)                        */
+  int32_t in_order;    /* 0 (default): a slot's batch starts on the device
+                        * as soon as it is launched, beside the previous
+                        * batch (the next batch's persistent kernel takes
+                        * over compute units as the previous one drains, and
+                        * the previous batch's post-processing then waits
+                        * for it); 1: each batch starts on the device after
+                        * the previous batch has finished there (its device
+                        * work is still queued ahead, so no launch gap) */
 } wl_server_config;
 
 /* Start a server on an uploaded ensemble; cfg may be NULL for defaults.

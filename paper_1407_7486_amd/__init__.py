@@ -80,7 +80,8 @@ class wl_action_out(ctypes.Structure):
 
 class wl_server_config(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("input_bytes", ctypes.c_size_t), ("result_bytes", ctypes.c_size_t)]
+                ("input_bytes", ctypes.c_size_t), ("result_bytes", ctypes.c_size_t),
+                ("in_order", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -451,10 +452,10 @@ class Server:
     numpy outputs alive until the ticket is released."""
 
     def __init__(self, ctx, ens, slots=2, max_batch=1024, input_bytes=8 << 20,
-                 result_bytes=512 << 20):
+                 result_bytes=512 << 20, in_order=False):
         self.ctx, self.ens = ctx, ens
         self.G = wl_ensemble_info(ens)[2]
-        cfg = wl_server_config(slots, max_batch, input_bytes, result_bytes)
+        cfg = wl_server_config(slots, max_batch, input_bytes, result_bytes, int(in_order))
         self.h = _vp()
         _check(_lib.wl_server_create(ctx, ens, ctypes.byref(cfg), ctypes.byref(self.h)), ctx)
         self._live = {}

@@ -51,6 +51,7 @@ struct Slot {
   void* d_res = nullptr;
   double* h_res = nullptr;  // pinned copy of sums, means, errors
   unsigned int* d_counter = nullptr;
+  hipEvent_t ev_done = nullptr;  // recorded after the batch's results are copied
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
   bool busy = false;
@@ -78,6 +79,7 @@ struct wl_server {
   int fatal = WL_OK;  // first HIP failure: the server then fails everything
   std::string err;
   int64_t n_batches = 0;
+  Slot* last = nullptr;  // the slot launched most recently (in-order mode)
 };
 
 namespace {
@@ -165,8 +167,10 @@ void pick_batch(wl_server* s, Slot* sl) {
   sl->prec = prec;
 }
 
-// Launches the slot's batch (without the lock).
-hipError_t launch_slot(wl_server* s, Slot* sl) {
+// Launches the slot's batch (without the lock).  prev: the slot launched
+// before it, whose batch this one waits for on the device (in-order mode;
+// nullptr: no wait).
+hipError_t launch_slot(wl_server* s, Slot* sl, Slot* prev) {
   std::vector<const wl_request*> rq;
   std::vector<wl::FieldArgs> fa;
   std::vector<wl::ReqPlan> pl;
@@ -185,10 +189,12 @@ hipError_t launch_slot(wl_server* s, Slot* sl) {
   // under the lock after this)
   const Clock::time_point now = Clock::now();
   for (Ticket* t : sl->reqs) t->t_launch = now;
+  if (e == hipSuccess && prev) e = hipStreamWaitEvent(sl->stream, prev->ev_done, 0);
   if (e == hipSuccess) e = hipGraphLaunch(sl->exec[sl->prec], sl->stream);
   const size_t out_b = sl->lay.head_bytes;
   if (e == hipSuccess)
     e = hipMemcpyAsync(sl->h_res, sl->d_res, out_b, hipMemcpyDeviceToHost, sl->stream);
+  if (e == hipSuccess) e = hipEventRecord(sl->ev_done, sl->stream);
   sl->done.store(false, std::memory_order_relaxed);
   if (e == hipSuccess) e = hipLaunchHostFunc(sl->stream, host_done, sl);
   return e;
@@ -229,8 +235,12 @@ void scheduler(wl_server* s) {
       sl->busy = true;
       any_busy = true;
       s->n_batches++;
+      // the previous slot's event is recorded by its own launch, which
+      // happened before this one (same thread)
+      Slot* prev = s->cfg.in_order && s->last && s->last != sl ? s->last : nullptr;
+      s->last = sl;
       lk.unlock();
-      const hipError_t e = launch_slot(s, sl);
+      const hipError_t e = launch_slot(s, sl, prev);
       lk.lock();
       if (e != hipSuccess) {
         sfail(s, WL_EHIP, "batch launch: %s", hipGetErrorString(e));
@@ -271,6 +281,8 @@ int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg
     if (cfg->max_batch < 1) return wl::fail(ctx, WL_EINVAL, "max_batch must be >= 1");
     if (cfg->input_bytes < 4096 || cfg->result_bytes < 4096)
       return wl::fail(ctx, WL_EINVAL, "slot budgets must be >= 4096 bytes");
+    if (cfg->in_order != 0 && cfg->in_order != 1)
+      return wl::fail(ctx, WL_EINVAL, "in_order must be 0 or 1");
     c = *cfg;
   }
   c.input_bytes = (c.input_bytes + 255) & ~(size_t)255;
@@ -290,6 +302,7 @@ int wl_server_create(wl_ctx* ctx, const wl_ens* ens, const wl_server_config* cfg
     if (e == hipSuccess) e = hipMalloc(&sl->d_res, c.result_bytes);
     if (e == hipSuccess)
       e = hipMalloc((void**)&sl->d_counter, wl::kBatchCounters * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl->ev_done, hipEventDisableTiming);
     s->slots.push_back(std::move(sl));
     if (e != hipSuccess) {
       wl_server* raw = s.release();
@@ -436,6 +449,7 @@ int wl_server_destroy(wl_server* s) {
     if (sl->d_in) (void)hipFree(sl->d_in);
     if (sl->d_res) (void)hipFree(sl->d_res);
     if (sl->d_counter) (void)hipFree(sl->d_counter);
+    if (sl->ev_done) (void)hipEventDestroy(sl->ev_done);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
   }
   delete s;

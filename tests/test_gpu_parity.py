@@ -380,11 +380,12 @@ def test_recomputation_of_a_partial_chunk(wl, ctx):
         wl.wl_ensemble_free(ens)
 
 
-def test_server_results_equal_alone(wl, ctx):
+@pytest.mark.parametrize("in_order", [False, True])
+def test_server_results_equal_alone(wl, ctx, in_order):
     """Continuous batching: requests submitted to the server (several
     batches, graph replays on two slots) give exactly wl_average's result for
     each request alone; a request larger than a slot's budget is refused."""
-    say("server")
+    say("server", "in order" if in_order else "overlapping")
     x, y = wlinputs.polygon_loops(512, 203, seed=29)
     ens = wl.wl_ensemble_upload(ctx, x, y, 8)
     try:
@@ -394,7 +395,8 @@ def test_server_results_equal_alone(wl, ctx):
             q["rho"] = q["rho"][: 1 + i % 9]
             q["T"] = q["T"][: 1 + (3 * i) % 17]
         # a small result budget forces several batches per slot
-        srv = wl.Server(ctx, ens, slots=2, max_batch=5, result_bytes=1 << 20)
+        srv = wl.Server(ctx, ens, slots=2, max_batch=5, result_bytes=1 << 20,
+                        in_order=in_order)
         try:
             tickets = [srv.submit(q) for q in reqs]
             for t in tickets:

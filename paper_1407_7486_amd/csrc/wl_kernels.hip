@@ -76,6 +76,45 @@ __device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double 
   return acc;
 }
 
+// acc * v + c with the coefficient c in a scalar register pair.  For the
+// per-loop code between segment walks: a coefficient held in vector
+// registers there lives across the walk and is spilled to scratch and
+// reloaded for every loop; a scalar pair is rebuilt by two s_mov.
+__device__ __forceinline__ double fma3s_f64(double acc, double v, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(v), "s"(c));
+  return r;
+}
+
+// Horner with every coefficient in scalar registers.  The first step is
+// c[DEG] v (rounded) + c[DEG-1]: an FMA of two constants would need two
+// scalar operands, and a start value c[DEG] in vector registers would be
+// spilled like a vector coefficient.
+template <int DEG>
+__device__ __forceinline__ double horner_s_f64(const double (&c)[DEG + 1], double v) {
+  double t, acc;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(t) : "v"(v), "s"(c[DEG]));
+  asm("v_add_f64 %0, %1, %2" : "=v"(acc) : "v"(t), "s"(c[DEG - 1]));
+#pragma unroll
+  for (int k = DEG - 2; k >= 0; --k) acc = fma3s_f64(acc, v, c[k]);
+  return acc;
+}
+
+// cos(2 pi r) for |r| <= 1/2: r = f + j/4 with j the nearest quarter turn
+// (f = r - j/4 is exact, |f| <= 1/8), then cos(2 pi f), -sin, -cos or sin
+// for j = 0, 1, 2, 3 (mod 4), each from its polynomial in f^2 (relative
+// error at FP64 rounding).  NaN in, NaN out.
+__device__ __forceinline__ double cos2pi(double r) {
+  const double j = rint(4.0 * r);
+  const double f = fma(-0.25, j, r);
+  const double v = f * f;
+  const double c = horner_s_f64<WL_COS2PI_F64_DEG>(WL_COS2PI_F64, v);
+  const double s = f * horner_s_f64<WL_SIN2PI_F64_DEG>(WL_SIN2PI_F64, v);
+  const int q = (int)j & 3;
+  const double m = (q & 1) ? s : c;
+  return (q == 1 || q == 2) ? -m : m;
+}
+
 // qa: phase weight, qb: spin integrand, as functions of rho^2 (FP32,
 // hardware transcendentals: v_exp/v_log are base 2, v_rcp/v_rsq 1 ulp).
 // Units (the epilogue constants cphi, cspin restore them):
@@ -490,7 +529,7 @@ __device__ __forceinline__ void loop_sums_f64seg(const double4* __restrict__ seg
 }
 
 // Per-loop epilogue in FP64: phase, spin exponent and w.  The phase is
-// reduced in revolutions (cos(Phi) = cospi(2 frac(Phi/2pi))).  The FP32
+// reduced in revolutions (cos(Phi) = cos(2 pi frac(Phi/2pi))).  The FP32
 // paths take cosh from the hardware exp2 of the fractional part of
 // S log2(e), scaled by the integer part in FP64 (relative error ~1e-7, no
 // overflow below FP64's range); the FP64 path forms cosh from the library
@@ -514,7 +553,7 @@ __device__ __forceinline__ double cosh_spin(double S) {
 template <bool SPIN, int PREC>
 __device__ __forceinline__ void wparts(double phi, double S, double& cw, double& ch) {
   const double rev = phi * 0.15915494309189533577;
-  cw = cospi(2.0 * (rev - rint(rev)));
+  cw = cos2pi(rev - rint(rev));
   ch = SPIN ? cosh_spin<PREC>(S) : 1.0;
 }
 
@@ -901,9 +940,10 @@ __device__ __forceinline__ void scale_point(const double* __restrict__ pa,
 // loops_per_sub barrier iterations.
 // Register budgets: the FP64 kernel is held to 128 VGPRs (4 waves per SIMD
 // instead of 3, its ~150 would fit three), the FP32 ones to 64 (8 waves,
-// four 8-wave workgroups per CU, instead of 6 at their 77).  The values
-// that no longer fit (lane constants) are reloaded from scratch once per
-// loop, outside the segment walk.
+// four 8-wave workgroups per CU, instead of 6 at their 77).  The FP32
+// kernels then spill three per-item values, reloaded after the item's last
+// loop; the FP64 one reloads three values once per loop, outside the
+// segment walk.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave)
 __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(

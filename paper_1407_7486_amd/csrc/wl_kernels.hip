@@ -328,6 +328,14 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
 // level) is summed plainly in FP32 and the block sums accumulate in FP64, so
 // the long sum over the loop carries no error growth with N; plain mode
 // sums every term in FP32.
+// Staged walk (compensated mode, every field but the sech^2 spinor one):
+// each wave copies 64 segments at a time into its own LDS buffer (one
+// 16-byte load per lane) and reads them back as broadcasts, one segment
+// ahead, so that the segment quantities enter the arithmetic from vector
+// registers (two-operand forms and an FMA with a literal) instead of scalar
+// ones.  Measured: rational -20%, constant -33%, Gaussian -2 to -5%, sech^2
+// scalar -1%, the sech^2 spinor walk +0.6% (it keeps the scalar loads); the
+// results are the same bits either way.
 // Rounding-error estimate (EST), returned in Q:
 //   EST 1  Q ~ sum_i qa_i^2, sampled from the first segment of every fetch
 //          of 8 (each sample standing for 8 segments; tail segments counted
@@ -336,6 +344,12 @@ __device__ __forceinline__ LaneF32 lane_consts(double rho, double s, double T,
 //          of A), qe_i the scale of qa_i's rounding (field_f32): the
 //          squared size of each term's rounding relative to u, the two
 //          parts of the cross product being summed apart.
+// Per-wave staging buffers of the FP32 segment walk, one of 64 segments for
+// each wave of a workgroup (every kernel that walks segments in FP32 runs
+// workgroups of at most 8 waves, fixed by its launch bounds).  One array for
+// the module, so that a kernel instantiating several walks holds one copy.
+__shared__ float4 g_stage[8][kWave];
+
 template <int KIND, bool SPIN, bool COMP, int EST = 0>
 __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
                                               int32_t n, const LaneF32& c,
@@ -392,6 +406,45 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
   };
   Acc s_ = {0.0f, 0.0f, 0.0f};  // plain mode: FP32 sums
   int32_t i = 0;
+  if constexpr (COMP && !(KIND == kSech2 && SPIN)) {
+    const int32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int32_t ln = threadIdx.x % kWave;
+    float4* buf = g_stage[wv];
+    for (; i + 64 <= n; i += 64) {
+      // every lane's reads of the previous 64 are issued before the buffer
+      // is refilled, and the refill before any read (LDS operations of a
+      // wave complete in order)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      buf[ln] = seg[i + ln];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+      for (int half = 0; half < 2; ++half) {
+        Acc p = {0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int quarter = 0; quarter < 4; ++quarter) {
+          // the index in a vector register: one address register with
+          // immediate offsets, not a copy from a scalar one per read
+          int32_t idx = 32 * half + 8 * quarter;
+          asm volatile("" : "+v"(idx));
+          float4 cur = buf[idx];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const float4 nxt = buf[idx + (k < 7 ? k + 1 : k)];
+            term(cur, p, k == 0 ? 1 : 0);
+            // accumulate here: left to itself the compiler defers the eight
+            // segments' accumulations to the end, holding their operands
+            asm volatile("" : "+v"(p.c), "+v"(p.d), "+v"(p.b));
+            cur = nxt;
+          }
+        }
+        add_block(p);
+      }
+    }
+  }
   if constexpr (COMP) {
     for (; i + 32 <= n; i += 32) {
       Acc p = {0.0f, 0.0f, 0.0f};

@@ -5,9 +5,11 @@
 // grid point j of the chunk and walks every segment of every loop of the
 // item in order.  The segment data of the loop being walked are the same
 // for all 64 lanes, so they arrive through wave-uniform (scalar) loads and
-// sit in SGPRs: one fetch of a segment serves 64 (rho, T) evaluations, and
-// the loop tile is reused across the whole grid without any cross-lane
-// traffic.  A lane's per-loop phase and spin sums therefore need no
+// sit in SGPRs, or (the compensated walks of every field but the sech^2
+// spinor one) are copied 64 at a time into a per-wave LDS buffer and read
+// back as broadcasts: one fetch of a segment serves 64 (rho, T)
+// evaluations, and the loop tile is reused across the whole grid.  A lane's
+// per-loop phase and spin sums therefore need no
 // wavefront reduction, and its FP64 group-sum accumulator has exactly one
 // owner and a fixed loop order (deterministic results).
 //

@@ -96,9 +96,8 @@ struct ReqDesc {
 };
 
 constexpr int kWavesPerWG = 4;  // batch and per-loop kernels
-// k_average: waves per workgroup (barrier-coupled), by precision; the FP64
-// kernel is held to 128 VGPRs (4 waves per SIMD), so it takes workgroups of
-// 4 waves, one per SIMD.
+// k_average: waves per workgroup (barrier-coupled), by precision: 8 for
+// the FP32 kernels, 4 (one per SIMD) for the FP64 ones.
 constexpr int avg_waves(int prec) { return prec == 2 ? 4 : 8; }
 constexpr int kWave = 64;
 

@@ -61,42 +61,54 @@ __device__ __forceinline__ float horner_f32(const float (&c)[DEG + 1], float v) 
 }
 
 // acc * v + c as the three-address v_fma_f64.  The compiler's choice for a
-// Horner step is the two-address v_fmac_f64, whose addend register is
-// overwritten; with a loop-invariant coefficient as the addend it then
-// copies the coefficient (a 64-bit move) before every step.
+// running sum acc + v c is the two-address v_fmac_f64, which is fine; this
+// form keeps a loop-invariant addend from being copied before every use.
 __device__ __forceinline__ double fma3_f64(double acc, double v, double c) {
   double r;
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(v), "v"(c));
   return r;
 }
 
-template <int DEG>
-__device__ __forceinline__ double horner_f64(const double (&c)[DEG + 1], double v) {
-  double acc = c[DEG];
-#pragma unroll
-  for (int k = DEG - 1; k >= 0; --k) acc = fma3_f64(acc, v, c[k]);
-  return acc;
-}
-
-// acc * v + c with the coefficient c in a scalar register pair.  For the
-// per-loop code between segment walks: a coefficient held in vector
-// registers there lives across the walk and is spilled to scratch and
-// reloaded for every loop; a scalar pair is rebuilt by two s_mov.
+// acc * v + c as the three-address v_fma_f64 with the coefficient c in a
+// scalar register pair.  Polynomial coefficients as vector operands are
+// loop-invariant values the compiler holds in vector registers across the
+// segment walk (two per coefficient, 54 polynomial coefficients in the FP64
+// walk and its epilogue), which under a register budget are spilled to
+// scratch and reloaded for every loop or segment; as scalar operands they
+// sit in scalar registers (constant-memory loads, or two s_mov each) and the
+// FMA reads them directly.  (The two-address v_fmac_f64 would overwrite its
+// addend, so a coefficient addend would first be copied into a vector
+// register at every step.)
 __device__ __forceinline__ double fma3s_f64(double acc, double v, double c) {
   double r;
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(v), "s"(c));
   return r;
 }
 
-// Horner with every coefficient in scalar registers.  The first step is
-// c[DEG] v (rounded) + c[DEG-1]: an FMA of two constants would need two
-// scalar operands, and a start value c[DEG] in vector registers would be
-// spilled like a vector coefficient.
+// Horner with every coefficient in scalar registers, for the per-loop
+// epilogue (between segment walks, where any vector register held across
+// the walk is spilled).  The first step is c[DEG] v (rounded) + c[DEG-1]:
+// an FMA of two constants would need two scalar operands, which a VOP3
+// instruction on this chip cannot read.
 template <int DEG>
 __device__ __forceinline__ double horner_s_f64(const double (&c)[DEG + 1], double v) {
   double t, acc;
   asm("v_mul_f64 %0, %1, %2" : "=v"(t) : "v"(v), "s"(c[DEG]));
   asm("v_add_f64 %0, %1, %2" : "=v"(acc) : "v"(t), "s"(c[DEG - 1]));
+#pragma unroll
+  for (int k = DEG - 2; k >= 0; --k) acc = fma3s_f64(acc, v, c[k]);
+  return acc;
+}
+
+// Horner for the FP64 segment walk: the leading coefficient in a vector
+// register pair (held across the walk, one pair per polynomial), the
+// others as scalar operands, so that the first step stays one FMA.  With
+// every coefficient a vector operand the FP64 sech^2 spinor kernel needed
+// 128 VGPRs (4 waves per SIMD); in this form it needs 60 (8 waves).
+template <int DEG>
+__device__ __forceinline__ double horner_sv_f64(const double (&c)[DEG + 1], double v) {
+  double acc;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(acc) : "v"(c[DEG]), "v"(v), "s"(c[DEG - 1]));
 #pragma unroll
   for (int k = DEG - 2; k >= 0; --k) acc = fma3s_f64(acc, v, c[k]);
   return acc;
@@ -228,7 +240,7 @@ __device__ __forceinline__ double rsq64(double x) {
 __device__ __forceinline__ double exp2_neg64(double t) {
   const double tc = -fmin(t, 4096.0);
   const double n = rint(tc);
-  const double p = horner_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, tc - n);
+  const double p = horner_sv_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, tc - n);
   return ldexp(p, (int)n);
 }
 
@@ -252,16 +264,16 @@ __device__ __forceinline__ void field_f64(double r2, const FieldArgs& f,
     qb = Eip * ip;
     const double v = r2 * f.inv_lam2_d;
     if (v < 0.25) {
-      qa = horner_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v) * f.inv_lam2_d;
+      qa = horner_sv_f64<WL_Q_SECH2_F64_DEG>(WL_Q_SECH2_F64, v) * f.inv_lam2_d;
     } else {
-      const double L = E * horner_f64<WL_LOG1P_F64_DEG>(WL_LOG1P_F64, E);
+      const double L = E * horner_sv_f64<WL_LOG1P_F64_DEG>(WL_LOG1P_F64, E);
       qa = fma(-(t * kLn2), Eip, kLn2 - L) * (q * q);
     }
   } else if constexpr (KIND == kGauss) {
     const double v = r2 * f.inv_lam2_d;
     const double E = exp2_neg64(v * kLog2e);
     qb = E;
-    qa = v < 0.5 ? horner_f64<WL_P_GAUSS_F64_DEG>(WL_P_GAUSS_F64, v) * f.inv_lam2_d
+    qa = v < 0.5 ? horner_sv_f64<WL_P_GAUSS_F64_DEG>(WL_P_GAUSS_F64, v) * f.inv_lam2_d
                  : (1.0 - E) * rcp64(r2);
   } else {
     const double r = rcp64(r2 + f.lam2_d);
@@ -587,13 +599,29 @@ __device__ __forceinline__ void loop_sums_f64seg(const double4* __restrict__ seg
 // reduced in revolutions (cos(Phi) = cos(2 pi frac(Phi/2pi))).  The FP32
 // paths take cosh from the hardware exp2 of the fractional part of
 // S log2(e), scaled by the integer part in FP64 (relative error ~1e-7, no
-// overflow below FP64's range); the FP64 path forms cosh from the library
-// exp.
+// overflow below FP64's range).  The FP64 path forms e^|S| = 2^t with
+// t = |S| log2(e) carried as t_hi + t_lo (the product's rounding, from an
+// FMA, and log2(e)'s own tail), n = rint(t_hi), 2^(t_hi - n) from the
+// exp2 polynomial of the segment walk with its coefficients as scalar
+// operands, and 2^t_lo as 1 + t_lo ln 2; e^-|S| by the Newton-refined
+// reciprocal.  A few ulp; beyond |S| = 709.78 e^|S| is inf (t_hi is held
+// below 1100 so that n fits an int), and NaN stays NaN.  (The library exp
+// held its coefficients in vector registers that were spilled and
+// reloaded for every loop.)
+constexpr double kLog2eLo = 2.0355273740931033e-17;  // log2(e) - kLog2e
+
 template <int PREC>
 __device__ __forceinline__ double cosh_spin(double S) {
   if constexpr (PREC == 2) {
-    const double e = exp(fabs(S));
-    return 0.5 * (e + 1.0 / e);
+    const double a = fabs(S);
+    const double th = a * kLog2e;
+    const double tl = fma(a, kLog2e, -th) + a * kLog2eLo;
+    const double tc = th > 1100.0 ? 1100.0 : th;
+    const double n = rint(tc);
+    const double p0 = horner_s_f64<WL_EXP2_F64_DEG>(WL_EXP2_F64, tc - n);
+    const double p = fma(p0 * tl, kLn2, p0);
+    const int ni = (int)n;
+    return 0.5 * (ldexp(p, ni) + ldexp(rcp64(p), -ni));
   } else {
     const double t = fabs(S) * 1.4426950408889634074;  // |S| log2(e)
     const double k = floor(t);
@@ -868,7 +896,7 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
 // G n_sub), so that the items of a small count, one chunk, lie side by side
 // and spread over every XCD and compute unit.  The split depends only on
 // the count, so a request gives the same bits alone and in a batch.
-constexpr int kEscWaves = 3;  // waves per SIMD of the recomputation kernels
+constexpr int kEscWaves = 6;  // waves per SIMD of the recomputation kernels
 __device__ __forceinline__ int64_t esc_items(int64_t rows, int32_t cnt) {
   return rows * (((int64_t)cnt + kWave - 1) / kWave);
 }
@@ -993,15 +1021,13 @@ __device__ __forceinline__ void scale_point(const double* __restrict__ pa,
 // about once per workgroup and then served from the caches.  Every wave,
 // including padding waves past the last item, runs the same
 // loops_per_sub barrier iterations.
-// Register budgets: the FP64 kernel is held to 128 VGPRs (4 waves per SIMD
-// instead of 3, its ~150 would fit three), the FP32 ones to 64 (8 waves,
-// four 8-wave workgroups per CU, instead of 6 at their 77).  The FP32
-// kernels then spill three per-item values, reloaded after the item's last
-// loop; the FP64 one reloads three values once per loop, outside the
-// segment walk.
+// Register budget 64 VGPRs, 8 waves per SIMD: the FP32 kernels (77
+// uncapped, 6 waves) then spill three per-item values, reloaded after the
+// item's last loop; the FP64 ones need at most 60 (their polynomial
+// coefficients are scalar operands), 8 waves in workgroups of 4.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
+__attribute__((amdgpu_waves_per_eu(8))) void k_average(
     const float4* __restrict__ seg, const double4* __restrict__ seg64,
     const float2* __restrict__ norm, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
@@ -1043,9 +1069,8 @@ __attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_average(
 
 // FP64 recomputation of the flagged grid points of an evaluation: the
 // G n_sub ceil(count / 64) items of escalate_item, grid-stride (four waves
-// per workgroup, no barrier).  Register budget 168 VGPRs, 3 waves per SIMD:
-// at 128 (4 waves) the sech^2 and Gaussian walks spill inside the segment
-// loop (the sech^2 spinor one 15 scratch accesses per segment).
+// per workgroup, no barrier).  Register budget 84 VGPRs, 6 waves per SIMD
+// (the sech^2 spinor walk needs 80).
 template <int KIND, bool SPIN>
 __global__ __launch_bounds__(kWavesPerWG * kWave)
 __attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate(
@@ -1100,13 +1125,11 @@ __global__ __launch_bounds__(256) void k_scale(const double* __restrict__ pa,
 // workgroups per CU): their three sets of sums need ~100, which would leave
 // room for two workgroups, and the few values spilled to scratch (live
 // across the sub-loop walks, not inside them) cost less than the lost
-// occupancy.  The FP64 kernels are held to 128 (4 waves per SIMD, as
-// k_average) for the same reason: uncapped, the sech^2 spinor one takes 178
-// (2 waves) and runs 1.46x longer per segment than k_average; capped, its
-// spills are again outside the segment walks and the two run at one rate.
+// occupancy.  The FP64 kernels need at most 75 and run at the same 6
+// waves per SIMD, spilling nothing inside a segment walk.
 template <int KIND, bool SPIN, int PREC>
 __global__ __launch_bounds__(avg_waves(PREC) * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 6))) void k_disc(
+__attribute__((amdgpu_waves_per_eu(6))) void k_disc(
     const float4* __restrict__ seg, const float4* __restrict__ sub,
     const double4* __restrict__ seg64, const double4* __restrict__ sub64, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g,
@@ -1201,13 +1224,11 @@ __device__ __forceinline__ int64_t take_item(unsigned int* counter) {
 // 5 at its 86): more waves hide the scalar-load and dispatch latencies of
 // the persistent item loop better than the spills it costs (measured
 // 2.20e12 -> 2.50e12 segment-evals/s on a 128-request batch).  The FP64
-// one is held to 128 (4 waves per SIMD, as k_average; 2 at its 199): a batch
-// of four FP64 spinor requests (sech^2, Gaussian, rational, constant) on
-// 16384 x 4096 loops and a 64 x 64 grid took 1972 ms, now 1289 (3 waves:
-// 1440), against 1166 for the four k_average launches.
+// one runs at the same 8 waves (it needs 64 VGPRs, two per-item values
+// spilled outside the walks).
 template <int PREC>
 __global__ __launch_bounds__(kWavesPerWG * kWave)
-__attribute__((amdgpu_waves_per_eu(PREC == 2 ? 4 : 8))) void k_batch(
+__attribute__((amdgpu_waves_per_eu(8))) void k_batch(
     const float4* __restrict__ seg, const double4* __restrict__ seg64,
     const float2* __restrict__ norm, int32_t n_ppl, const BatchHeader* __restrict__ hdr,
     unsigned int* __restrict__ counter, int64_t loops_per_group) {

@@ -884,21 +884,31 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
 // = g n_sub + sub of the evaluation's partial sums, chunk c of the flagged
 // points): the sub-range's loops are walked in FP64 from the raw points
 // (loop_sums_f64raw, the FP64 path's arithmetic) for the flagged points
-// list[64 c .. 64 c + 63] (ascending, cnt of them), and each point's sum of
-// w over the sub-range is written over the item's FP32 partial sum.  A
-// chunk of more than 32 points takes one per lane, the wave walking each
-// loop together (its points come in through scalar loads that the wave
-// shares).  A chunk of at most 32 (16) points leaves lanes free: the wave's
-// lanes then form 2 (4) copies of the chunk, copy r walking loops l0 + r,
-// l0 + r + 2 (4), ... through vector loads (2 or 4 loops per wave, so a
-// load touches at most 4 cache lines), and a fixed butterfly adds the
-// copies' sums.  Items are numbered chunk-major, k = c rows + gs (rows =
-// G n_sub), so that the items of a small count, one chunk, lie side by side
-// and spread over every XCD and compute unit.  The split depends only on
-// the count, so a request gives the same bits alone and in a batch.
+// list[C c .. C c + C - 1] (ascending, cnt of them), and each point's sum
+// of w over the sub-range is written over the item's FP32 partial sum.  The
+// chunk size C is 64, halved down to 8 while the items would not fill two
+// rounds of the chip's wave slots (a few flagged points then still spread
+// over every SIMD).  A chunk of more than 32 points takes one per lane, the
+// wave walking each loop together (its points come in through scalar loads
+// that the wave shares).  A chunk of at most P = 32, 16 or 8 points leaves
+// lanes free: the wave's lanes then form R = 64/P copies of the chunk, copy
+// r walking loops l0 + r, l0 + r + R, ... through vector loads (R loops per
+// wave, so a load touches at most 8 cache lines), and a fixed butterfly
+// adds the copies' sums.  Items are numbered chunk-major, k = c rows + gs
+// (rows = G n_sub), so that the items of a small count lie side by side and
+// spread over every XCD and compute unit.  The split depends only on the
+// count, so a request gives the same bits alone and in a batch.
 constexpr int kEscWaves = 6;  // waves per SIMD of the recomputation kernels
+// two rounds of wave slots: 1024 SIMDs (256 CUs) x kEscWaves, twice
+constexpr int64_t kEscFill = 2 * 1024 * kEscWaves;
+__device__ __forceinline__ int32_t esc_chunk(int64_t rows, int32_t cnt) {
+  int32_t C = kWave;
+  while (C > 8 && rows * (((int64_t)cnt + C - 1) / C) < kEscFill) C >>= 1;
+  return C;
+}
 __device__ __forceinline__ int64_t esc_items(int64_t rows, int32_t cnt) {
-  return rows * (((int64_t)cnt + kWave - 1) / kWave);
+  const int32_t C = esc_chunk(rows, cnt);
+  return rows * (((int64_t)cnt + C - 1) / C);
 }
 
 template <int KIND, bool SPIN>
@@ -918,11 +928,12 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
   int64_t l1 = l0 + loops_per_sub;
   if (l1 > (g + 1) * loops_per_group) l1 = (g + 1) * loops_per_group;
   const int32_t lane = (int32_t)(threadIdx.x % kWave);
-  const int32_t cnt_c = min(kWave, cnt - chunk * kWave);  // wave-uniform
-  const int32_t P = cnt_c <= 16 ? 16 : cnt_c <= 32 ? 32 : kWave;
+  const int32_t C = esc_chunk(rows, cnt);                // wave-uniform
+  const int32_t cnt_c = min(C, cnt - chunk * C);         // 1 .. C
+  const int32_t P = cnt_c <= 8 ? 8 : cnt_c <= 16 ? 16 : cnt_c <= 32 ? 32 : kWave;
   const int32_t p = lane % P, r = lane / P;
   const bool esc = p < cnt_c;
-  const int32_t pg = list[chunk * kWave + (esc ? p : cnt_c - 1)];
+  const int32_t pg = list[chunk * C + (esc ? p : cnt_c - 1)];
   const double rho = rho_g[pg / n_T];
   const double T = T_g[pg % n_T];
   const double s = sqrt(T);
@@ -945,7 +956,8 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
                                    f, A, B);
       acc += epilogue<SPIN, 2>(A, B, T, n_ppl, f, phi, S);
     }
-    if (P == 16) acc += __shfl_xor(acc, 16);
+    if (P == 8) acc += __shfl_xor(acc, 8);
+    if (P <= 16) acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
   }
   if (esc && r == 0) out[gs * n_pts + pg] = acc;
@@ -1068,7 +1080,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_average(
 }
 
 // FP64 recomputation of the flagged grid points of an evaluation: the
-// G n_sub ceil(count / 64) items of escalate_item, grid-stride (four waves
+// esc_items(G n_sub, count) items of escalate_item, grid-stride (four waves
 // per workgroup, no barrier).  Register budget 84 VGPRs, 6 waves per SIMD
 // (the sech^2 spinor walk needs 80).
 template <int KIND, bool SPIN>
@@ -1304,7 +1316,7 @@ __attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate_batch(
 
 // First recomputation item of each request of a batch, per variant (one
 // thread, in request order): for the request's variant v,
-// esc_begin[v][r + 1] = esc_begin[v][r] + G n_sub_r ceil(count_r / 64);
+// esc_begin[v][r + 1] = esc_begin[v][r] + esc_items(G n_sub_r, count_r);
 // the other variants' tables repeat their entry.
 __global__ void k_esc_begin(const BatchHeader* __restrict__ hdr, int32_t n_groups,
                             int64_t loops_per_group) {

@@ -229,7 +229,8 @@ def c3_run(wl, ctx, torch, dev, precision_report):
     """The precision-stress configuration at its full size: 131072 d-loops of
     8192 points (generated on the device from the seed-0 stream), sech^2 tube
     eB0 = 20, lambda = 4, 32 rho_cm in [0, 5], 48 T in [1e-3, 10] (eB0 T up
-    to 200), spinor: one timed compensated-FP32 and one FP64 evaluation."""
+    to 200), spinor: one timed evaluation each in compensated FP32, in the
+    Kahan-compensated study mode and in FP64."""
     import numpy as np
 
     import wlinputs
@@ -247,7 +248,7 @@ def c3_run(wl, ctx, torch, dev, precision_report):
             "fp_err": torch.empty((rho.size, T.size), dtype=torch.float64, device=dev),
             "escalated": torch.empty((rho.size, T.size), dtype=torch.uint8, device=dev)}
     res = {}
-    for prec, name in ((wl.WL_FP32C, "fp32c"), (wl.WL_FP64, "fp64")):
+    for prec, name in ((wl.WL_FP32C, "fp32c"), (wl.WL_FP32K, "fp32k"), (wl.WL_FP64, "fp64")):
         log(f"[bench] c3 {name}")
         wl.wl_set_timing(ctx, True)
         torch.cuda.synchronize()
@@ -266,6 +267,9 @@ def c3_run(wl, ctx, torch, dev, precision_report):
            "fp32c_over_fp64": res["fp64"][1]["call_s"] / res["fp32c"][1]["call_s"]}
     r64 = dict(res["fp64"][0], err=None)
     out["fp32c_vs_fp64"] = precision_report(res["fp32c"][0], r64)
+    # the study mode of Kahan-compensated FP32 sums (no guard)
+    out["fp32k"] = res["fp32k"][1]
+    out["fp32k_vs_fp64"] = precision_report(res["fp32k"][0], r64)
     out["finite"] = bool(np.isfinite(res["fp32c"][0]["mean"]).all())
     return out
 
@@ -508,6 +512,12 @@ def main():
                 "fp32c_vs_fp64": precision_report(r32, r64)}
         log(f"[bench] fp64 {v64:.4e} seg/s, kernel {k64:.1f} ms; "
             f"{fp64['fp32c_vs_fp64']}")
+        # the study mode of Kahan-compensated FP32 sums (no guard), one step
+        dtk, kk = run(ens, d_rho, d_T, wl.WL_FP32K, 0, 1, outs)
+        fp64["fp32k"] = {"value": seg_per_step / dtk, "ms_per_step": 1e3 * dtk,
+                         "kernel_ms": kk, "fp32k_vs_fp64": precision_report(host(outs), r64)}
+        log(f"[bench] fp32k {seg_per_step / dtk:.4e} seg/s, kernel {kk:.1f} ms; "
+            f"{fp64['fp32k']['fp32k_vs_fp64']}")
 
     disc = None
     if args.disc_steps > 0 and cfg["n_ppl"] % 4 == 0:

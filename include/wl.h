@@ -79,10 +79,20 @@ typedef struct wl_field {
  *           estimated rounding error exceeds half the mean tolerance
  *           1e-6 M_S (see wl_result), are recomputed in FP64.
  * WL_FP32   plain FP32 sums, no guard (precision-study mode).
- * WL_FP64   FP64 throughout.                                               */
+ * WL_FP64   FP64 throughout.
+ * WL_FP32K  FP32 segment arithmetic as WL_FP32C, each phase and spin sum
+ *           Kahan-compensated in FP32 (sum and running compensation)
+ *           instead of the block sums, FP64 epilogue and group sums, no
+ *           guard: the "FP32 with compensated summation" column of the
+ *           precision study (Sec. 4.3).  A precision-study mode offered by
+ *           wl_average, wl_average_ex(_device), wl_average_async and
+ *           wl_per_loop; the discretisation estimate, batches and the server
+ *           reject it (WL_EINVAL).  The rounding estimate (fp_err) is stated
+ *           as for WL_FP32C, with no recomputation.                         */
 #define WL_FP32C 0
 #define WL_FP32 1
 #define WL_FP64 2
+#define WL_FP32K 3
 
 /* ---- ensemble upload flags -------------------------------------------- */
 #define WL_HOST_PTR 0   /* y_x, y_y are host pointers                       */
@@ -159,7 +169,7 @@ int wl_ensemble_info(const wl_ens* ens, int64_t* n_loops, int32_t* n_ppl,
 /* Wilson-loop ensemble average over the grid rho[n_rho] x T[n_T]
  * (Sec. 3.2 for w per loop, Sec. 4.2.3 for groups and error).
  * rho >= 0 and T > 0, all finite; spin 0 = scalar, 1 = spinor; precision
- * one of WL_FP32C, WL_FP32, WL_FP64.
+ * one of WL_FP32C, WL_FP32, WL_FP64, WL_FP32K.
  * Outputs (host, caller-owned, each may be NULL):
  *   mean       [n_rho][n_T]    (1/N_l) sum_l w_l
  *   err        [n_rho][n_T]    standard error of the group means (NaN if

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libwl.so")
 
 WL_OK, WL_EINVAL, WL_ENOMEM, WL_EHIP, WL_ENODEV = 0, -1, -2, -3, -4
 WL_CONST, WL_SECH2, WL_GAUSS, WL_RATIONAL = 0, 1, 2, 3
-WL_FP32C, WL_FP32, WL_FP64 = 0, 1, 2
+WL_FP32C, WL_FP32, WL_FP64, WL_FP32K = 0, 1, 2, 3
 WL_HOST_PTR, WL_DEVICE_PTR = 0, 1
 WL_DISC_PAPER, WL_DISC_FULL = 0, 1
 WL_SUB_CIRCLE, WL_SUB_SQUARE, WL_SUB_TRIANGLE = 0, 1, 2

@@ -119,8 +119,15 @@ int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision
   if (!ens) return fail(ctx, WL_EINVAL, "ensemble is NULL");
   if (ens->ctx != ctx) return fail(ctx, WL_EINVAL, "ensemble belongs to another context");
   if (spin != 0 && spin != 1) return fail(ctx, WL_EINVAL, "spin must be 0 or 1");
-  if (precision < WL_FP32C || precision > WL_FP64)
+  if (precision < WL_FP32C || precision > WL_FP32K)
     return fail(ctx, WL_EINVAL, "unknown precision %d", precision);
+  return WL_OK;
+}
+
+int check_not_study(wl_ctx* ctx, int32_t precision) {
+  if (precision == WL_FP32K)
+    return fail(ctx, WL_EINVAL,
+                "WL_FP32K is a precision-study mode of wl_average and wl_per_loop only");
   return WL_OK;
 }
 
@@ -847,6 +854,7 @@ int wl_average_batch(wl_ctx* ctx, const wl_ens* ens, const wl_request* reqs,
   for (int32_t r = 0; r < n_reqs; ++r) {
     const wl_request& q = reqs[r];
     if ((rc = check_common(ctx, ens, q.spin, q.precision)) ||
+        (rc = check_not_study(ctx, q.precision)) ||
         (rc = check_field(ctx, &q.field, &fa[r])) ||
         (rc = check_grid(ctx, q.rho, q.n_rho, q.T, q.n_T))) {
       std::string m = ctx->err;
@@ -992,6 +1000,7 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   ctx->err.clear();
   int rc = check_common(ctx, ens, spin, precision);
   if (rc) return rc;
+  if ((rc = check_not_study(ctx, precision))) return rc;
   wl::FieldArgs fa;
   if ((rc = check_field(ctx, field, &fa))) return rc;
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;
@@ -1066,6 +1075,7 @@ int wl_discretisation(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   ctx->err.clear();
   int rc = check_common(ctx, ens, spin, precision);
   if (rc) return rc;
+  if ((rc = check_not_study(ctx, precision))) return rc;
   wl::FieldArgs fa;
   if ((rc = check_field(ctx, field, &fa))) return rc;
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;

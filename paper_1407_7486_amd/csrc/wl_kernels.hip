@@ -511,6 +511,67 @@ __device__ __forceinline__ void loop_sums_f32(const float4* __restrict__ seg,
   Q = EST == 1 ? 8.0 * (double)qs : (double)qs;
 }
 
+// FP32 walk with Kahan-compensated sums (WL_FP32K, a precision-study mode
+// in place of the block sums of the compensated mode): the geometry of the
+// compensated walk, and each of the three sums (c qa, d_y qa, qb) carried
+// in FP32 with its running compensation e (y = x - e, t = s + y,
+// e = (t - s) - y, s = t), returned in FP64 as s - e and combined as
+// there.  Q is the EST 1 estimate of loop_sums_f32.
+template <int KIND, bool SPIN>
+__device__ __forceinline__ void loop_sums_f32k(const float4* __restrict__ seg, int32_t n,
+                                               const LaneF32& c, const FieldArgs& f,
+                                               double& A, double& B, double& Q) {
+  constexpr bool kSpinSum = SPIN && KIND != kConst;
+  const float Rf = KIND == kSech2 ? c.R_s : c.R;
+  const float Uf = KIND == kSech2 ? c.U_s : c.U;
+  float thr = KIND == kSech2 ? kSech2ThrS : KIND == kGauss ? f.thr : 0.0f;
+  asm volatile("" : "+v"(thr));
+  float sc = 0.0f, ec = 0.0f, sd = 0.0f, ed = 0.0f, sb = 0.0f, eb = 0.0f, qs = 0.0f;
+  auto kadd = [](float& sum, float& comp, float x) {
+    const float y = x - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  };
+  // sample: as in loop_sums_f32's EST 1 (units of 8 segments)
+  auto term = [&](const float4 s4, int sample) {
+    float r2;
+    if constexpr (KIND == kSech2) {
+      const float mx = fmaf(c.s_s, s4.x, c.rho_s_hi) + c.rho_s_lo;
+      r2 = fmaf(mx, mx, fmaf(c.R_s, s4.y, 1e-30f));
+    } else if constexpr (KIND != kConst) {
+      const float mx = fmaf(c.s_hi, s4.x, c.rho_hi) + c.rho_lo;
+      r2 = fmaf(mx, mx, fmaf(c.R, s4.y, 1e-30f));
+    } else {
+      r2 = 1.0f;
+    }
+    float qa, qb, qe;
+    field_f32<KIND, true>(r2, f, thr, qa, qb, qe);
+    kadd(sc, ec, s4.w * qa);
+    kadd(sd, ed, s4.z * qa);
+    if constexpr (kSpinSum) kadd(sb, eb, qb);
+    if (sample == 1) qs = fmaf(qa, qa, qs);
+    if (sample == 2) qs = fmaf(qa * 0.125f, qa, qs);
+  };
+  int32_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    float4 sv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sv[k] = seg[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) term(sv[k], k == 0 ? 1 : 0);
+  }
+  for (; i < n; ++i) term(seg[i], 2);
+  const double dc = (double)sc - (double)ec;
+  const double dd = (double)sd - (double)ed;
+  const double db = (double)sb - (double)eb;
+  const double R = Rf;
+  const double U = Uf;
+  A = R * dc + U * dd;
+  B = kSpinSum ? db : (double)n;
+  Q = 8.0 * (double)qs;
+}
+
 // FP64 path over FP64 segment quantities (m_x, m_y^2, d_y, c) of whole
 // loops or sub-loops, each formed from the FP32 points (exact but for one
 // rounding of m_y^2 and c) and read from an array: the midpoint's radius
@@ -801,7 +862,10 @@ __device__ __forceinline__ void avg_loop(const float4* __restrict__ seg,
     R = s * s;
     U = rho * s;
   } else {
-    loop_sums_f32<KIND, SPIN, PREC == 0, 1>(seg + l * n_ppl, n_ppl, c, f, A, B, Q);
+    if constexpr (PREC == 3)
+      loop_sums_f32k<KIND, SPIN>(seg + l * n_ppl, n_ppl, c, f, A, B, Q);
+    else
+      loop_sums_f32<KIND, SPIN, PREC == 0, 1>(seg + l * n_ppl, n_ppl, c, f, A, B, Q);
     R = KIND == kSech2 ? c.R_s : c.R;
     U = KIND == kSech2 ? c.U_s : c.U;
   }
@@ -1488,6 +1552,8 @@ __global__ __launch_bounds__(kWavesPerWG * kWave) void k_per_loop(
   double A, B, Q, phi, S;
   if constexpr (PREC == 2) {
     loop_sums_f64seg<KIND, SPIN>(seg64 + l * n_ppl + sl.seg_off, sl.m, rho, s, f, A, B);
+  } else if constexpr (PREC == 3) {
+    loop_sums_f32k<KIND, SPIN>(seg + l * n_ppl + sl.seg_off, sl.m, c, f, A, B, Q);
   } else {
     loop_sums_f32<KIND, SPIN, PREC == 0, PREC == 0 ? 2 : 0>(seg + l * n_ppl + sl.seg_off,
                                                             sl.m, c, f, A, B, Q);
@@ -1796,6 +1862,21 @@ hipError_t launch_pl_t(const FieldArgs& f, const float4* seg, const double4* seg
     default: return hipErrorInvalidValue;                                       \
   }
 
+// The same over the four precisions, WL_FP32K (3) included: the launchers
+// of the evaluations that offer the compensated-sum study mode.
+#define WL_DISPATCH4(FN, ...)                                                   \
+  switch (precision == 3 ? 24 + f.kind * 2 + spin : f.kind * 6 + spin * 3 + precision) { \
+    case 24: return FN<kConst, false, 3>(__VA_ARGS__);                          \
+    case 25: return FN<kConst, true, 3>(__VA_ARGS__);                           \
+    case 26: return FN<kSech2, false, 3>(__VA_ARGS__);                          \
+    case 27: return FN<kSech2, true, 3>(__VA_ARGS__);                           \
+    case 28: return FN<kGauss, false, 3>(__VA_ARGS__);                          \
+    case 29: return FN<kGauss, true, 3>(__VA_ARGS__);                           \
+    case 30: return FN<kRational, false, 3>(__VA_ARGS__);                       \
+    case 31: return FN<kRational, true, 3>(__VA_ARGS__);                        \
+    default: WL_DISPATCH(FN, __VA_ARGS__)                                       \
+  }
+
 }  // namespace
 
 hipError_t launch_prep(const float* d_x, const float* d_y, int64_t n_loops,
@@ -1832,8 +1913,8 @@ hipError_t launch_average(int precision, int spin, const FieldArgs& f,
                           int32_t n_ppl, const double* d_rho, const double* d_T,
                           int32_t n_T, int32_t n_pts, const Sched& s, double* d_out,
                           double* d_out_a, double* d_out_v, hipStream_t stream) {
-  WL_DISPATCH(launch_avg_t, f, d_seg, d_seg64, d_norm, n_ppl, d_rho, d_T, n_T, n_pts, s,
-              d_out, d_out_a, d_out_v, stream)
+  WL_DISPATCH4(launch_avg_t, f, d_seg, d_seg64, d_norm, n_ppl, d_rho, d_T, n_T, n_pts, s,
+               d_out, d_out_a, d_out_v, stream)
 }
 
 hipError_t launch_scale_escalate(int precision, int spin, const FieldArgs& f,
@@ -1873,8 +1954,8 @@ hipError_t launch_per_loop(int precision, int spin, const FieldArgs& f,
                            int32_t n_pts, int64_t loop0, int64_t n_loops,
                            double* d_phase, double* d_spin, double* d_w,
                            hipStream_t stream) {
-  WL_DISPATCH(launch_pl_t, f, d_seg, d_seg64, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
-              loop0, n_loops, d_phase, d_spin, d_w, stream)
+  WL_DISPATCH4(launch_pl_t, f, d_seg, d_seg64, d_x, d_y, n_ppl, sl, d_rho, d_T, n_T, n_pts,
+               loop0, n_loops, d_phase, d_spin, d_w, stream)
 }
 
 hipError_t launch_prep_sub(const float* d_x, const float* d_y, int64_t n_loops,

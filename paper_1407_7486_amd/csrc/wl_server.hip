@@ -327,6 +327,7 @@ int wl_server_submit(wl_server* s, const wl_request* req, int64_t* ticket) {
   if (s->fatal != WL_OK) return sfail(s, s->fatal, "server failed earlier");
   // validation reuses the context's checks; their message is copied here
   int rc = wl::check_common(ctx, s->ens, req->spin, req->precision);
+  if (!rc) rc = wl::check_not_study(ctx, req->precision);
   if (!rc) rc = wl::check_field(ctx, &req->field, &t->fa);
   if (!rc) rc = wl::check_grid(ctx, req->rho, req->n_rho, req->T, req->n_T);
   if (rc) return sfail(s, rc, "%s", ctx->err.c_str());

@@ -19,7 +19,7 @@ FIELDS = {
     "gauss": (2, 2.0, 0.9),
     "rational": (3, 1.5, 0.8),
 }
-PRECS = {"fp32c": 0, "fp32": 1, "fp64": 2}
+PRECS = {"fp32c": 0, "fp32": 1, "fp64": 2, "fp32k": 3}
 RHO = np.array([0.0, 0.3, 1.1, 2.5, 5.0])
 TGRID = np.geomspace(1e-3, 30.0, 13)  # 65 grid points: one full chunk + 1
 
@@ -83,7 +83,8 @@ def test_per_loop_and_means_small(wl, ctx, small, fname, spin, pname):
     # the scale of each mean, and (compensated FP32) the stated rounding
     # estimate bounds the actual error
     np.testing.assert_allclose(r["scale"], m_s, rtol=1e-12 if prec == 2 else 1e-3)
-    r3 = check_fp_err(mean, o_mean, r["fp_err"], r["escalated"], m_s) if prec == 0 else 0.0
+    r3 = (check_fp_err(mean, o_mean, r["fp_err"], r["escalated"], m_s) if prec in (0, 3)
+          else 0.0)
     assert set(np.unique(r["escalated"])) <= ({0, 1} if prec == 0 else {0})
     say("worst error/tolerance: phase %.3g spin %.3g w %.3g mean %.3g sums %.3g; "
         "mean error / stated estimate %.3g" % (*r1, *r2, r3))
@@ -115,6 +116,28 @@ def test_narrow_and_wide_tubes(wl, ctx, small, lam, pname):
         o_mean, _, _ = oracle.stats(o["group_sums"], 128)
         check_means(prec, mean, sums, o_mean, o["group_sums"],
                     *mean_scales(o["w"], o["spin"], 4, 1))
+
+
+def test_study_mode_only_in_average_and_per_loop(wl, ctx, small):
+    """WL_FP32K runs in wl_average and wl_per_loop; the discretisation
+    estimate, batches and the server refuse it with WL_EINVAL."""
+    x, y, ens = small
+    say("fp32k refusals")
+    fld = wl.field(1, 1.3, 0.7)
+    rho, T = RHO[:3], TGRID[:4]
+    mean, _, _ = wl.wl_average(ctx, ens, fld, rho, T, 1, wl.WL_FP32K)
+    assert np.isfinite(mean).all()
+    with pytest.raises(RuntimeError, match="WL_FP32K"):
+        wl.wl_discretisation(ctx, ens, fld, rho, T, 1, wl.WL_FP32K)
+    q = dict(kind=1, eB0=1.3, lam=0.7, rho=rho, T=T, spin=1, precision=wl.WL_FP32K)
+    with pytest.raises(RuntimeError, match="WL_FP32K"):
+        wl.wl_average_batch(ctx, ens, [q])
+    srv = wl.Server(ctx, ens, slots=2)
+    try:
+        with pytest.raises(RuntimeError, match="WL_FP32K"):
+            srv.submit(q)
+    finally:
+        srv.close()
 
 
 def test_subrange_and_ragged_loop_window(wl, ctx, small):

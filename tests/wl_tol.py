@@ -26,6 +26,15 @@ rounding estimate of each mean (fp_err) must also bound the actual error.
 
 WL_FP32 (plain sums, no guard) is a precision-study mode and only has to
 agree to 1e-3 relative, with the conditioning terms at u = 2^-24.
+
+WL_FP32K (Kahan-compensated FP32 sums, no guard) is the study mode of
+compensated summation: its sums carry no error growth with N, so what
+remains is each term's rounding, as for FP64 but at u = 2^-24: per loop
+1e-5 max(1, |Phi|) (the combine and epilogue, a few u) plus 16 u sqrt(sum
+t_i^2) (the terms' random rounding) plus 2 u sum |t_i| (the hardware
+elementary functions' bias), S to 1e-5 max(1, S), and each mean within the
+library's stated rounding estimate, whose model is that per-term rounding;
+the mean bar itself is the study modes' 1e-3 M_S.
 """
 import numpy as np
 
@@ -35,6 +44,7 @@ TOL = {
     2: dict(phase=1e-12, cond=16 * U64, sys=2 * U64, spin=1e-12, mean=1e-12),  # WL_FP64
     0: dict(phase=1e-5, cond=0.0, sys=0.0, spin=1e-5, mean=1e-6),              # WL_FP32C
     1: dict(phase=1e-3, cond=16 * U32, sys=2 * U32, spin=1e-3, mean=1e-3),     # WL_FP32
+    3: dict(phase=1e-5, cond=16 * U32, sys=2 * U32, spin=1e-5, mean=1e-3),     # WL_FP32K
 }
 
 

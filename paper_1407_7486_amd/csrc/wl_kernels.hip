@@ -72,8 +72,8 @@ __device__ __forceinline__ double fma3_f64(double acc, double v, double c) {
 // acc * v + c as the three-address v_fma_f64 with the coefficient c in a
 // scalar register pair.  Polynomial coefficients as vector operands are
 // loop-invariant values the compiler holds in vector registers across the
-// segment walk (two per coefficient, 54 polynomial coefficients in the FP64
-// walk and its epilogue), which under a register budget are spilled to
+// segment walk (two per coefficient: 53 in the FP64 walk's polynomials, 16
+// more in the per-loop cosine), which under a register budget are spilled to
 // scratch and reloaded for every loop or segment; as scalar operands they
 // sit in scalar registers (constant-memory loads, or two s_mov each) and the
 // FMA reads them directly.  (The two-address v_fmac_f64 would overwrite its

@@ -91,6 +91,17 @@ def test_noalloc_scratch_size_matches_the_header(wl):
     assert wl.WL_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
 
 
+def test_binding_constants_match_the_header(wl):
+    """Every integer #define of include/wl.h that the binding also names
+    (precision modes, field kinds, flags, error codes) has the same value."""
+    txt = open(HEADER).read()
+    defs = {n: int(v) for n, v in re.findall(r"#define (WL_[A-Z0-9_]+) (-?\d+)\b", txt)}
+    shared = {n for n in defs if hasattr(wl, n)}
+    assert {"WL_FP32C", "WL_FP32", "WL_FP64", "WL_FP32K", "WL_SECH2"} <= shared
+    bad = {n: (defs[n], getattr(wl, n)) for n in shared if getattr(wl, n) != defs[n]}
+    assert not bad, bad
+
+
 def test_no_device_is_reported_cleanly(wl):
     import torch
     if torch.cuda.device_count() > 0:

@@ -694,10 +694,12 @@ def main():
                    "n_groups": G, "field": kname, "eB0": cfg["eB0"], "lambda": cfg["lam"],
                    "spin": spin, "precision": "fp32c",
                    "precision_note": "FP32 segment arithmetic; each 32-segment block summed "
-                                     "in FP32 and the block sums in FP64 (in place of FP32 "
-                                     "Kahan summation); FP64 epilogue and group sums; loops "
-                                     "and means the rounding estimate cannot bring within "
-                                     "1e-5 (phase) and 1e-6 M_S (mean) recomputed in FP64",
+                                     "in FP32 and the block sums in FP64; FP64 epilogue and "
+                                     "group sums; loops and means the rounding estimate "
+                                     "cannot bring within 1e-5 (phase) and 1e-6 M_S (mean) "
+                                     "recomputed in FP64.  FP32 with Kahan-compensated sums "
+                                     "and no recomputation is the study mode reported under "
+                                     "fp64.fp32k and c3.fp32k",
                    "generator": "d-loops, seed 0"},
         "roofline": roofline, "cpu_baseline": cpu, "fp64": fp64, "c3": c3, "c4": c4,
         "serve": serve,

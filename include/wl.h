@@ -85,9 +85,9 @@ typedef struct wl_field {
  *           instead of the block sums, FP64 epilogue and group sums, no
  *           guard: the "FP32 with compensated summation" column of the
  *           precision study (Sec. 4.3).  A precision-study mode offered by
- *           wl_average, wl_average_ex(_device), wl_average_async and
- *           wl_per_loop; the discretisation estimate, batches and the server
- *           reject it (WL_EINVAL).  The rounding estimate (fp_err) is stated
+ *           wl_average, wl_average_ex(_device), wl_average_async,
+ *           wl_per_loop and wl_subloop_per_loop; the discretisation
+ *           estimate, batches and the server reject it (WL_EINVAL).  The rounding estimate (fp_err) is stated
  *           as for WL_FP32C, with no recomputation.                         */
 #define WL_FP32C 0
 #define WL_FP32 1

@@ -127,7 +127,7 @@ int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision
 int check_not_study(wl_ctx* ctx, int32_t precision) {
   if (precision == WL_FP32K)
     return fail(ctx, WL_EINVAL,
-                "WL_FP32K is a precision-study mode of wl_average and wl_per_loop only");
+                "WL_FP32K is a precision-study mode of wl_average and the per-loop calls only");
   return WL_OK;
 }
 
@@ -1000,7 +1000,6 @@ int wl_subloop_per_loop(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
   ctx->err.clear();
   int rc = check_common(ctx, ens, spin, precision);
   if (rc) return rc;
-  if ((rc = check_not_study(ctx, precision))) return rc;
   wl::FieldArgs fa;
   if ((rc = check_field(ctx, field, &fa))) return rc;
   if ((rc = check_grid(ctx, rho, n_rho, T, n_T))) return rc;

@@ -67,7 +67,7 @@ int hip_fail(wl_ctx* ctx, hipError_t e, const char* what);
 int check_field(wl_ctx* ctx, const wl_field* f, FieldArgs* a);
 int check_grid(wl_ctx* ctx, const double* rho, int32_t n_rho, const double* T, int32_t n_T);
 int check_common(wl_ctx* ctx, const wl_ens* ens, int32_t spin, int32_t precision);
-// WL_EINVAL for WL_FP32K, which only wl_average and wl_per_loop offer.
+// WL_EINVAL for WL_FP32K, which only wl_average and the per-loop calls offer.
 int check_not_study(wl_ctx* ctx, int32_t precision);
 Sched make_sched(const wl_ctx* ctx, const wl_ens* e, int32_t n_pts);
 // FP64 segment array of an ensemble, built on first use on `stream`

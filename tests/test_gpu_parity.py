@@ -119,7 +119,7 @@ def test_narrow_and_wide_tubes(wl, ctx, small, lam, pname):
 
 
 def test_study_mode_only_in_average_and_per_loop(wl, ctx, small):
-    """WL_FP32K runs in wl_average and wl_per_loop; the discretisation
+    """WL_FP32K runs in wl_average and the per-loop calls; the discretisation
     estimate, batches and the server refuse it with WL_EINVAL."""
     x, y, ens = small
     say("fp32k refusals")

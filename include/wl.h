@@ -75,9 +75,10 @@ typedef struct wl_field {
  *           sums over blocks of 32 segments, the block sums accumulated in
  *           FP64); FP64 per-loop epilogue and FP64 group sums.  Guarded by
  *           a rounding estimate: per-loop values whose FP32 phase may miss
- *           the phase tolerance 1e-5 max(1, |Phi|), and ensemble means whose
- *           estimated rounding error exceeds half the mean tolerance
- *           1e-6 M_S (see wl_result), are recomputed in FP64.
+ *           the phase tolerance 1e-5 max(1, |Phi|) are recomputed in FP64;
+ *           for an ensemble mean whose estimated rounding error exceeds half
+ *           the mean tolerance 1e-6 M_S (see wl_result), the loop
+ *           sub-ranges that carry that estimate are recomputed in FP64.
  * WL_FP32   plain FP32 sums, no guard (precision-study mode).
  * WL_FP64   FP64 throughout.
  * WL_FP32K  FP32 segment arithmetic as WL_FP32C, each phase and spin sum
@@ -87,8 +88,9 @@ typedef struct wl_field {
  *           precision study (Sec. 4.3).  A precision-study mode offered by
  *           wl_average, wl_average_ex(_device), wl_average_async,
  *           wl_per_loop and wl_subloop_per_loop; the discretisation
- *           estimate, batches and the server reject it (WL_EINVAL).  The rounding estimate (fp_err) is stated
- *           as for WL_FP32C, with no recomputation.                         */
+ *           estimate, batches and the server reject it (WL_EINVAL).  The
+ *           rounding estimate (fp_err) is stated as for WL_FP32C, with no
+ *           recomputation.                                                   */
 #define WL_FP32C 0
 #define WL_FP32 1
 #define WL_FP64 2
@@ -211,11 +213,16 @@ int wl_average(wl_ctx* ctx, const wl_ens* ens, const wl_field* field,
  *                              through sin(Phi) cosh(S)
  *                              and added in quadrature, plus 8 u M_S for the
  *                              roundings shared by all loops (u = 2^-24 for
- *                              the FP32 modes, 2^-53 for FP64 and for
- *                              recomputed points)
- *   escalated  [n_rho][n_T]    1 where WL_FP32C recomputed the point in FP64
- *                              (the random part of fp_err above 0.5e-6 M_S),
- *                              else 0 */
+ *                              the FP32 modes, 2^-53 for FP64); for a
+ *                              recomputed point, that of the loop sub-ranges
+ *                              left in FP32
+ *   escalated  [n_rho][n_T]    1 where WL_FP32C recomputed in FP64 part of
+ *                              the point (the random part of fp_err above
+ *                              0.5e-6 M_S): the loop sub-ranges (G n_sub of
+ *                              them) whose rounding accumulators exceed
+ *                              1/(G n_sub) of the largest total that would
+ *                              pass, so that the sub-ranges left in FP32
+ *                              pass; else 0 */
 typedef struct wl_result {
   double* mean;
   double* err;

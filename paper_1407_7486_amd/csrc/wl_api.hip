@@ -661,9 +661,14 @@ struct DevOut {
 // recomputation flags and the compacted list of flagged points with its
 // count.
 static size_t flag_bytes(int32_t n_pts) { return ((size_t)n_pts + 7) & ~(size_t)7; }
+// The sub-range partial sums of w (when split), the scale and rounding
+// accumulators, the scale of each mean (read by the FP64 recomputation,
+// also when the caller does not ask for it), one flag byte and one list
+// entry per grid point.
 static size_t eval_scratch_bytes(const wl::Sched& s, int64_t n_groups, int32_t n_pts) {
   const size_t part = (size_t)n_groups * s.n_sub * n_pts;
-  return 8 * part * (s.n_sub > 1 ? 3 : 2) + flag_bytes(n_pts) + 4 * ((size_t)n_pts + 1);
+  return 8 * part * (s.n_sub > 1 ? 3 : 2) + 8 * (size_t)n_pts + flag_bytes(n_pts) +
+         4 * ((size_t)n_pts + 1);
 }
 
 // Enqueue one evaluation; grid and outputs are device memory: the main
@@ -706,7 +711,8 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
   double* p_w = s.n_sub > 1 ? (double*)buf : o.sums;
   double* p_a = (double*)buf + (s.n_sub > 1 ? part : 0);
   double* p_v = p_a + part;
-  uint8_t* flags = (uint8_t*)(p_v + part);
+  double* scale = o.scale ? o.scale : p_v + part;
+  uint8_t* flags = (uint8_t*)(p_v + part + n_pts);
   int32_t* list = (int32_t*)(flags + flag_bytes(n_pts));
   hipError_t e = hipSuccess;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -723,7 +729,7 @@ static int average_device(wl_ctx* ctx, const wl_ens* ens, const wl::FieldArgs& f
   }
   if (e == hipSuccess)
     e = wl::launch_scale_escalate(precision, spin, fa, ens->d_x, ens->d_y, ens->n_ppl, d_rho,
-                                  d_T, n_T, n_pts, s, ens->n_loops, p_a, p_v, o.scale,
+                                  d_T, n_T, n_pts, s, ens->n_loops, p_a, p_v, scale,
                                   o.fp_err, flags, list, p_w, ctx->stream);
   if (e == hipSuccess && s.n_sub > 1)
     e = wl::launch_reduce_sub(p_w, ens->n_groups, s.n_sub, n_pts, o.sums, ctx->stream);

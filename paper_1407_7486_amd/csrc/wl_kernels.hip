@@ -944,6 +944,22 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+constexpr double kEscalate = 0.5e-6;
+constexpr double kDecideK = 16.0;
+
+// A flagged point recomputes in FP64 only the sub-range rows whose rounding
+// accumulator exceeds thr = B / rows, B being the largest accumulator sum
+// that still passes the decision (kDecideK u32 sqrt(B) / N_l = kEscalate
+// M_S): the rows left in FP32 then sum to at most rows thr = B, so the
+// point's FP32 remainder passes the same test as a point never flagged.
+// Where a few loops carry the estimate (a loop through the tube's core
+// with a large spin factor) that is a few rows; where every row carries its
+// share, all of them.
+__device__ __forceinline__ double esc_row_threshold(double ms, int64_t n_loops, int64_t rows) {
+  const double b = kEscalate * ms * (double)n_loops / (kDecideK * kU32);
+  return b * b / (double)rows;
+}
+
 // The FP64 recomputation of the flagged grid points, in work items (row gs
 // = g n_sub + sub of the evaluation's partial sums, chunk c of the flagged
 // points): the sub-range's loops are walked in FP64 from the raw points
@@ -984,6 +1000,8 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
                                               int64_t rows, int32_t n_sub,
                                               int64_t loops_per_group, int64_t loops_per_sub,
                                               const int32_t* __restrict__ list, int32_t cnt,
+                                              const double* __restrict__ pv,
+                                              const double* __restrict__ scale,
                                               double* __restrict__ out) {
   const int32_t chunk = (int32_t)(k / rows);
   const int64_t gs = k % rows;
@@ -998,6 +1016,11 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
   const int32_t p = lane % P, r = lane / P;
   const bool esc = p < cnt_c;
   const int32_t pg = list[chunk * C + (esc ? p : cnt_c - 1)];
+  // only the rows that carry the point's estimate are recomputed; an item
+  // none of whose points needs its row does nothing
+  const int64_t n_loops = loops_per_group * (rows / n_sub);
+  const bool need = esc && pv[gs * n_pts + pg] > esc_row_threshold(scale[pg], n_loops, rows);
+  if (__ballot(need) == 0) return;
   const double rho = rho_g[pg / n_T];
   const double T = T_g[pg % n_T];
   const double s = sqrt(T);
@@ -1024,7 +1047,7 @@ __device__ __forceinline__ void escalate_item(const float* __restrict__ X,
     if (P <= 16) acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
   }
-  if (esc && r == 0) out[gs * n_pts + pg] = acc;
+  if (need && r == 0) out[gs * n_pts + pg] = acc;
 }
 
 // The flagged grid points of one evaluation in ascending order, list[0 ..
@@ -1072,8 +1095,6 @@ __device__ __forceinline__ void compact_flags(const uint8_t* __restrict__ flags,
 // phase error stays below 18 u sqrt(sum_i t_i^2); at kDecideK = 16 a point
 // left in FP32 is then within half the tolerance even when one loop
 // carries the mean.
-constexpr double kEscalate = 0.5e-6;
-constexpr double kDecideK = 16.0;
 __device__ __forceinline__ void scale_point(const double* __restrict__ pa,
                                             const double* __restrict__ pv, int64_t rows,
                                             int32_t n_pts, int64_t n_loops, int32_t prec,
@@ -1087,7 +1108,18 @@ __device__ __forceinline__ void scale_point(const double* __restrict__ pa,
   const double u = prec == 2 ? kU64 : kU32;
   const double rnd = u * sqrt(sv) / (double)n_loops;
   esc = prec == 0 && kDecideK * rnd > kEscalate * ms;
-  fe = (esc ? kU64 / kU32 : 1.0) * (kPhaseK * rnd + kSysK * u * ms);
+  if (!esc) {
+    fe = kPhaseK * rnd + kSysK * u * ms;
+  } else {
+    // the rows left in FP32 (esc_row_threshold) and their estimate
+    const double thr = esc_row_threshold(ms, n_loops, rows);
+    double rest = 0.0;
+    for (int64_t r = 0; r < rows; ++r) {
+      const double v = pv[r * n_pts + p];
+      if (!(v > thr)) rest += v;
+    }
+    fe = kPhaseK * u * sqrt(rest) / (double)n_loops + kSysK * u * ms;
+  }
 }
 
 // ------------------------------------------------------------- kernels
@@ -1153,7 +1185,8 @@ __attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate(
     const float* __restrict__ X, const float* __restrict__ Y, int32_t n_ppl,
     const double* __restrict__ rho_g, const double* __restrict__ T_g, int32_t n_T,
     int32_t n_pts, FieldArgs f, Sched sc, const int32_t* __restrict__ list,
-    const int32_t* __restrict__ count, double* __restrict__ out) {
+    const int32_t* __restrict__ count, const double* __restrict__ pv,
+    const double* __restrict__ scale, double* __restrict__ out) {
   const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t cnt = __builtin_amdgcn_readfirstlane(*count);
   const int64_t rows = sc.n_items / sc.n_chunks;
@@ -1161,7 +1194,8 @@ __attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate(
   for (int64_t k = (int64_t)blockIdx.x * kWavesPerWG + wave; k < total;
        k += (int64_t)gridDim.x * kWavesPerWG)
     escalate_item<KIND, SPIN>(X, Y, n_ppl, rho_g, T_g, n_T, n_pts, f, k, rows, sc.n_sub,
-                              sc.loops_per_group, sc.loops_per_sub, list, cnt, out);
+                              sc.loops_per_group, sc.loops_per_sub, list, cnt, pv, scale,
+                              out);
 }
 
 // The flagged points of one evaluation, compacted (compact_flags).
@@ -1374,7 +1408,8 @@ __attribute__((amdgpu_waves_per_eu(kEscWaves))) void k_escalate_batch(
     const int32_t cnt = __builtin_amdgcn_readfirstlane(*q.count);
     escalate_item<KIND, SPIN>(X, Y, n_ppl, q.rho, q.T, q.n_T, q.n_pts, q.f,
                               item - wave_uniform(esc_begin[lo]), (int64_t)n_groups * q.n_sub,
-                              q.n_sub, loops_per_group, q.loops_per_sub, q.list, cnt, q.out);
+                              q.n_sub, loops_per_group, q.loops_per_sub, q.list, cnt, q.out_v,
+                              q.scale, q.out);
   }
 }
 
@@ -1785,7 +1820,7 @@ template <int KIND, bool SPIN>
 hipError_t launch_esc_t(const FieldArgs& f, const float* x, const float* y, int32_t n_ppl,
                         const double* rho, const double* T, int32_t n_T, int32_t n_pts,
                         const Sched& s, const uint8_t* flags, int32_t* list, int32_t* count,
-                        double* out, hipStream_t st) {
+                        const double* pv, const double* scale, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, flags, n_pts, list,
                      count);
   hipError_t e = hipGetLastError();
@@ -1796,7 +1831,7 @@ hipError_t launch_esc_t(const FieldArgs& f, const float* x, const float* y, int3
   int64_t n_wg = (s.n_items + kWavesPerWG - 1) / kWavesPerWG;
   if (n_wg > 4096) n_wg = 4096;
   hipLaunchKernelGGL((k_escalate<KIND, SPIN>), dim3((uint32_t)n_wg), dim3(kWavesPerWG * kWave),
-                     0, st, x, y, n_ppl, rho, T, n_T, n_pts, f, s, list, count, out);
+                     0, st, x, y, n_ppl, rho, T, n_T, n_pts, f, s, list, count, pv, scale, out);
   return hipGetLastError();
 }
 
@@ -1933,7 +1968,7 @@ hipError_t launch_scale_escalate(int precision, int spin, const FieldArgs& f,
   switch (f.kind * 2 + spin) {
 #define WL_ESC(K, SP)                                                                   \
   return launch_esc_t<K, SP>(f, d_x, d_y, n_ppl, d_rho, d_T, n_T, n_pts, s, d_flags, d_list, \
-                             d_list + n_pts, d_out, stream)
+                             d_list + n_pts, d_out_v, d_scale, d_out, stream)
     case 0: WL_ESC(kConst, false);
     case 1: WL_ESC(kConst, true);
     case 2: WL_ESC(kSech2, false);

@@ -340,9 +340,9 @@ def test_batch_recomputation_every_variant(wl, ctx):
     """One compensated-FP32 batch whose requests span all four field kinds
     and both spins, with points recomputed in FP64 in every scalar request:
     each request's outputs equal the request evaluated alone, bit for bit,
-    the recomputed means meet the FP64 bar against the oracle and the
-    others their stated estimate; a batch of one request (the smallest
-    result buffer) equals it too."""
+    every mean (recomputed or not) meets its stated estimate and the mean
+    bar against the oracle; a batch of one request (the smallest result
+    buffer) equals it too."""
     say("batch recomputation, every variant")
     x, y = wlinputs.polygon_loops(256, 203, seed=23)
     ens = wl.wl_ensemble_upload(ctx, x, y, 8)
@@ -376,9 +376,10 @@ def test_recomputation_of_a_partial_chunk(wl, ctx):
     (the wave splits into two copies of the chunk, each walking every other
     loop): sech^2 B0 = 20, lambda = 4, scalar, 6 rho x 7 T, where the
     oracle's rounding criterion puts 24 points above 3.7x the threshold and
-    the other 18 below 0.03x.  The recomputed means meet the FP64 bar
-    against the oracle, the others their stated estimate; the same request
-    in a batch gives the same bits."""
+    the other 18 below 0.03x.  Every mean meets its stated estimate (for a
+    recomputed one that of the loop sub-ranges left in FP32) and the mean
+    bar against the oracle; the same request in a batch gives the same
+    bits."""
     say("recomputation, 24 flagged points")
     x, y = wlinputs.polygon_loops(256, 203, seed=23)
     ens = wl.wl_ensemble_upload(ctx, x, y, 8)

@@ -15,8 +15,9 @@ loop |dPhi| <= 1e-5 max(1, |Phi|) (the library recomputes in FP64 every
 (loop, point) whose FP32 rounding estimate exceeds it), |dS| <= 1e-5
 max(1, S), and ensemble means and group sums within 1e-6 of the scale
     M_S = (1/N_l) sum_l |w_l| max(1, S_l)
-(the library recomputes in FP64 every grid point whose estimated rounding
-error exceeds half of that).  For scalar loops (S = 0, |w| <= 1) M_S is the
+(for every grid point whose estimated rounding error exceeds half of that,
+the library recomputes in FP64 the loop sub-ranges carrying the estimate,
+until the sub-ranges left in FP32 pass).  For scalar loops (S = 0, |w| <= 1) M_S is the
 mean |w| and the bar at most 1e-6 absolute.  For spinors FP32 carries the
 loop geometry, T and the field scales to relative precision 2^-24, so S has
 an error of order u S that cosh turns into a relative error of order
@@ -109,17 +110,16 @@ def check_means(prec, mean, sums, o_mean, o_sums, o_w_abs_mean, o_w_abs_group):
 
 def check_fp_err(mean, o_mean, fp_err, escalated, scale):
     """The library's stated rounding estimate of each compensated-FP32 mean
-    bounds its actual error against the oracle.  Where the library recomputed
-    the mean in FP64 (escalated), its estimate is FP64's, of the size of the
-    oracle's own rounding, so there the FP64 parity bar 1e-12 scale applies
-    instead.  Returns the worst error / estimate ratio over the other points."""
+    bounds its actual error against the oracle.  A flagged point (escalated)
+    was recomputed in FP64 over the loop sub-ranges that carried its
+    estimate; its stated estimate is that of the sub-ranges left in FP32,
+    which pass the same test as a point never flagged, so the same check
+    applies to every point.  Returns the worst error / estimate ratio."""
     dm = np.abs(mean - o_mean)
-    esc = escalated.astype(bool)
-    bad = ~esc & (dm > fp_err)
+    ratio = dm / np.maximum(fp_err, 1e-300)
+    bad = dm > fp_err
     assert not bad.any(), (
-        f"mean error above the stated estimate at {int(bad.sum())} points; "
-        f"worst {np.max(np.where(esc, 0, dm / np.maximum(fp_err, 1e-300))):.3g}x")
-    lim64 = TOL[2]["mean"] * scale
-    assert (dm[esc] <= lim64[esc]).all(), (
-        f"recomputed mean beyond the FP64 bar: worst {np.max((dm / lim64)[esc]):.3g}x")
-    return float(np.max(np.where(esc, 0.0, dm / np.maximum(fp_err, 1e-300))))
+        f"mean error above the stated estimate at {int(bad.sum())} points "
+        f"({int((bad & escalated.astype(bool)).sum())} of them recomputed); "
+        f"worst {np.max(ratio):.3g}x")
+    return float(np.max(ratio))

@@ -336,6 +336,16 @@ def _escalating_requests():
             for k in range(4) for sp in (0, 1)]
 
 
+def remainder_passes(r):
+    """After the FP64 recomputation of a flagged point's dominant loop
+    sub-ranges, its stated estimate (that of the sub-ranges left in FP32)
+    passes the decision: its random part 32 u sqrt(sum v) / N_l is at most
+    twice the decision's 0.5e-6 M_S, its shared part 8 u M_S."""
+    esc = r["escalated"].astype(bool)
+    lim = (1e-6 + 8 * 2.0 ** -24) * r["scale"] * (1 + 1e-9)
+    assert np.all(r["fp_err"][esc] <= lim[esc]), float(np.max((r["fp_err"] / lim)[esc]))
+
+
 def test_batch_recomputation_every_variant(wl, ctx):
     """One compensated-FP32 batch whose requests span all four field kinds
     and both spins, with points recomputed in FP64 in every scalar request:
@@ -361,6 +371,7 @@ def test_batch_recomputation_every_variant(wl, ctx):
             m_s, g_s = mean_scales(o["w"], o["spin"], 8, q["spin"])
             check_fp_err(ob["mean"], o_mean, ob["fp_err"], ob["escalated"], m_s)
             check_means(0, ob["mean"], ob["group_sums"], o_mean, o["group_sums"], m_s, g_s)
+            remainder_passes(ob)
             if not q["spin"]:
                 assert ob["escalated"].any(), (q["kind"], "no point recomputed")
         say("batch of one request")
@@ -396,6 +407,7 @@ def test_recomputation_of_a_partial_chunk(wl, ctx):
         m_s, g_s = mean_scales(o["w"], o["spin"], 8, 0)
         check_fp_err(r["mean"], o_mean, r["fp_err"], r["escalated"], m_s)
         check_means(0, r["mean"], r["group_sums"], o_mean, o["group_sums"], m_s, g_s)
+        remainder_passes(r)
         ob = wl.wl_average_batch(ctx, ens, [dict(kind=1, eB0=20.0, lam=4.0, rho=rho, T=T,
                                                  spin=0, precision=0)], full=True)[0]
         for k in wl.RESULT_KEYS:
